@@ -1,0 +1,88 @@
+/*
+ * dugks_oracle.h -- plain, slow FP64 CPU oracle of the incompressible DUGKS
+ * step with body force (Wu, Shi, Chai & Wang, arXiv:1411.6121).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this code; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no source, header, table
+ * or helper with the HIP implementation.
+ *
+ * The step follows the Appendix algorithm (steps 1-10) literally, over the
+ * explicit point sets X_c (cell centres), X_cg (ghost centres), X_b (face
+ * mid-points) and X_bc (interface cross points: 2-D corners, 3-D edge
+ * mid-points), with the readings of the paper listed in the design doc.
+ *
+ * Array layout at the interface (same as the product's, documented there):
+ *   distributions  f[q][z][y][x]  (x fastest), q in the lattice order below
+ *   vector fields  v[d][z][y][x]
+ *   scalar fields  s[z][y][x]
+ */
+#ifndef DUGKS_ORACLE_H
+#define DUGKS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_PERIODIC = 0, OR_NEQ_VELOCITY = 1, OR_NEQ_PRESSURE = 2, OR_BOUNCE_BACK = 3 };
+enum { OR_UNIFORM = 0, OR_TANH = 1 };
+
+typedef struct {
+    int lattice;        /* 9 (D2Q9) or 19 (D3Q19) */
+    int n[3];           /* cells per axis, n[2] == 1 for D2Q9 */
+    double L[3];        /* domain length per axis */
+    int mesh[3];        /* OR_UNIFORM or OR_TANH per axis */
+    double k_stretch;   /* tanh stretch constant k */
+    double rho0, RT, tau, dt;
+    double G[3];        /* uniform part of the acceleration */
+    double omega, phase;/* time factor g(t) = cos(omega t + phase) */
+    int bc[6];          /* sides -x,+x,-y,+y,-z,+z */
+    double uw[6][3];    /* wall velocity per side (velocity BCs) */
+    double pw[6];       /* wall pressure per side (pressure BC) */
+} oracle_cfg;
+
+/* lattice table: e[q*3+a] in {-1,0,1}, w[q]; returns Q or -1 */
+int oracle_lattice(int lattice, int* e, double* w);
+
+/* mesh of one axis: faces[n+1], centres[n+2] (ghost, 0..n-1, ghost) */
+int oracle_mesh(const oracle_cfg* cfg, int axis, double* faces, double* centres);
+
+/* discrete incompressible equilibrium and force term at one point (all q) */
+int oracle_feq(const oracle_cfg* cfg, double rho, const double* u, double* feq);
+int oracle_force_term(const oracle_cfg* cfg, double rho, const double* u,
+                      const double* G, double* S);
+
+/* f~0 = feq(rho,u) - dt/2 S(rho,u,G(x,t0)); rho, u, force nullable */
+int oracle_init(const oracle_cfg* cfg, const double* rho, const double* u,
+                const double* force, double t0, double* f_out);
+
+/* one step t_n -> t_n + dt; force nullable (spatial part G^(x), [D][cells]) */
+int oracle_step(const oracle_cfg* cfg, const double* f_in, double* f_out,
+                const double* force, double t_n);
+
+/* rho, u (D comps), p at time t; each output nullable.
+ * totals (nullable, 6): sum V rho, sum V j_x, sum V j_y, sum V j_z,
+ * 1/2 sum V |u|^2, number of non-finite values in f */
+int oracle_moments(const oracle_cfg* cfg, const double* f, const double* force,
+                   double t, double* rho, double* u, double* p, double* totals);
+
+/* reverse mode of one step on a fully periodic mesh:
+ *   lam_n      = (d f_{n+1} / d f_n)^T lam_np1
+ *   grad_force += (d f_{n+1} / d force)^T lam_np1   (nullable) */
+int oracle_step_adjoint(const oracle_cfg* cfg, const double* f_n, const double* force,
+                        double t_n, const double* lam_np1, double* lam_n,
+                        double* grad_force);
+
+/* reverse mode of oracle_init with rho = rho0 everywhere:
+ *   grad_u     += (d f0 / d u)^T lam0       (nullable)
+ *   grad_force += (d f0 / d force)^T lam0   (nullable) */
+int oracle_init_adjoint(const oracle_cfg* cfg, const double* u, const double* force,
+                        double t0, const double* lam0, double* grad_u, double* grad_force);
+
+/* number of OpenMP threads the oracle uses */
+int oracle_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

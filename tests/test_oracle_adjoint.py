@@ -1,0 +1,109 @@
+"""Pins of the oracle's tape-free reverse mode: <J v, w> from central finite
+differences of the forward step against <v, J^T w> from the adjoint.
+
+The step is a polynomial in (f~, G^) (the velocity divides by the constant
+rho0), so central differences are accurate to O(eps^2)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import field, perturb
+
+
+def setup(lat, stretch=0):
+    if lat == 9:
+        d = dict(lattice=9, n=(5, 4, 1), L=(5.0, 4.0, 1.0), mesh=(stretch, stretch, 0), k_stretch=1.5)
+    else:
+        d = dict(lattice=19, n=(3, 4, 5), L=(3.0, 4.0, 5.0), mesh=(stretch,) * 3, k_stretch=1.5)
+    d.update(rho0=1.0, RT=1 / 3, tau=0.45, dt=0.5, bc=(0,) * 6, G=(1e-3, -5e-4, 2e-4), omega=0.7, phase=0.3)
+    D, Q, shp = O.dims(d)
+    Gf = field(21, (D,) + shp, 2e-3)
+    f = perturb(22, O.init(d, rho=1 + field(23, shp, 0.02), u=field(24, (D,) + shp, 0.05), force=Gf), 1e-2)
+    return d, f, Gf
+
+
+@pytest.mark.parametrize("lat,stretch", [(9, 0), (9, 1), (19, 0)])
+def test_step_adjoint_dot_product(lat, stretch):
+    d, f, Gf = setup(lat, stretch)
+    t = 0.4
+    v = field(25, f.shape, 1.0)
+    w = field(26, f.shape, 1.0)
+    vg = field(27, Gf.shape, 1.0)
+    eps = 1e-5
+    jv = (O.step(d, f + eps * v, Gf, t) - O.step(d, f - eps * v, Gf, t)) / (2 * eps)
+    jg = (O.step(d, f, Gf + eps * 1e-2 * vg, t) - O.step(d, f, Gf - eps * 1e-2 * vg, t)) / (2 * eps * 1e-2)
+    gG = np.zeros_like(Gf)
+    jtw = O.step_adjoint(d, f, w, force=Gf, t=t, grad_force=gG)
+    lhs, rhs = np.vdot(jv, w), np.vdot(v, jtw)
+    assert rhs == pytest.approx(lhs, rel=5e-9)
+    lhs_g, rhs_g = np.vdot(jg, w), np.vdot(vg, gG)
+    assert rhs_g == pytest.approx(lhs_g, rel=1e-7)
+
+
+def test_step_adjoint_rejects_walls():
+    d, f, Gf = setup(9)
+    d["bc"] = (0, 0, 1, 1, 0, 0)
+    with pytest.raises(ValueError):
+        O.step_adjoint(d, f, f)
+
+
+def test_init_adjoint_matches_fd():
+    d, _, Gf = setup(9)
+    D, Q, shp = O.dims(d)
+    u = field(28, (D,) + shp, 0.05)
+    w = field(29, (Q,) + shp, 1.0)
+    vu = field(30, u.shape, 1.0)
+    vg = field(31, Gf.shape, 1.0)
+    gu, gg = np.zeros_like(u), np.zeros_like(Gf)
+    O.init_adjoint(d, w, u=u, force=Gf, t0=0.2, grad_u=gu, grad_force=gg)
+    eps = 1e-5
+    ju = (O.init(d, u=u + eps * vu, force=Gf, t0=0.2) - O.init(d, u=u - eps * vu, force=Gf, t0=0.2)) / (2 * eps)
+    jg = (O.init(d, u=u, force=Gf + eps * vg, t0=0.2) - O.init(d, u=u, force=Gf - eps * vg, t0=0.2)) / (2 * eps)
+    assert np.vdot(vu, gu) == pytest.approx(np.vdot(ju, w), rel=1e-9)
+    assert np.vdot(vg, gg) == pytest.approx(np.vdot(jg, w), rel=1e-8)
+
+
+def test_rollout_gradient_matches_fd():
+    # loss = mean of the squared final velocity after a short rollout; the
+    # chained adjoint (init VJP + step VJPs + read-out) against central FD on
+    # a few force components
+    d, _, Gf = setup(9)
+    D, Q, shp = O.dims(d)
+    nsteps = 4
+    u0 = field(32, (D,) + shp, 0.02)
+    target = field(33, (D,) + shp, 0.02)
+
+    def loss(G, u0_):
+        f = O.init(d, u=u0_, force=G)
+        f = O.run(d, f, nsteps, force=G)
+        _, u, _, _ = O.moments(d, f, force=G, t=nsteps * d["dt"])
+        return np.mean((u - target) ** 2)
+
+    # reverse
+    fs = [O.init(d, u=u0, force=Gf)]
+    for k in range(nsteps):
+        fs.append(O.step(d, fs[-1], Gf, k * d["dt"]))
+    _, u, _, _ = O.moments(d, fs[-1], force=Gf, t=nsteps * d["dt"])
+    du = 2 * (u - target) / u.size
+    e, _ = O.lattice(9)
+    xi = np.sqrt(3 * d["RT"]) * e[:, :D]
+    lam = np.tensordot(xi, du, axes=(1, 0)) / d["rho0"]
+    gG = np.zeros_like(Gf)
+    T = nsteps * d["dt"]
+    gG += np.cos(d["omega"] * T + d["phase"]) * d["dt"] / 2 * du  # read-out u carries + dt/2 G
+    for k in reversed(range(nsteps)):
+        lam = O.step_adjoint(d, fs[k], lam, force=Gf, t=k * d["dt"], grad_force=gG)
+    gu = np.zeros_like(u0)
+    O.init_adjoint(d, lam, u=u0, force=Gf, t0=0.0, grad_u=gu, grad_force=gG)
+    for idx in [(0, 0, 1, 2), (1, 0, 3, 4), (0, 0, 0, 0)]:
+        eps = 1e-5
+        Gp, Gm = Gf.copy(), Gf.copy()
+        Gp[idx] += eps
+        Gm[idx] -= eps
+        fd = (loss(Gp, u0) - loss(Gm, u0)) / (2 * eps)
+        assert gG[idx] == pytest.approx(fd, rel=1e-6, abs=1e-14)
+        up, um = u0.copy(), u0.copy()
+        up[idx] += eps
+        um[idx] -= eps
+        fd = (loss(Gf, up) - loss(Gf, um)) / (2 * eps)
+        assert gu[idx] == pytest.approx(fd, rel=1e-6, abs=1e-14)
