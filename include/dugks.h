@@ -1,0 +1,232 @@
+/*
+ * dugks.h -- C ABI of the MI355X (gfx950) incompressible-DUGKS library.
+ *
+ * One time step of the incompressible discrete unified gas-kinetic scheme
+ * with body force of Wu, Shi, Chai & Wang (arXiv:1411.6121), its adjoint,
+ * and a batched form, for the D2Q9 and D3Q19 velocity sets on uniform and
+ * tanh-stretched Cartesian meshes.  Every stage runs in hand-written HIP
+ * kernels; this header is the whole interface.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * Data layout (all device arrays are dense, C-contiguous, 256-byte aligned
+ * is recommended, element type = the context dtype):
+ *   distribution state  f[q][z][y][x]   x fastest, Q = 9 or 19 planes
+ *   vector field        v[d][z][y][x]   d < D (2 or 3 components)
+ *   scalar field        s[z][y][x]
+ * For D2Q9, nz = 1.  Velocity order (e = (ex, ey, ez) in {-1,0,1}^3):
+ *   D2Q9  : ex outer, ey inner (the order printed in Sec. II.C);
+ *           rest state at q = 4, opposite of q is 8 - q.
+ *   D3Q19 : ex outer, ey middle, ez inner, dropping the 8 corners
+ *           |e|^2 = 3; rest state at q = 9, opposite of q is 18 - q;
+ *           weights 1/3 (rest), 1/18 (|e|^2 = 1), 1/36 (|e|^2 = 2).
+ *   Discrete velocities xi_q = sqrt(3 RT) e_q (Sec. II.C).
+ * The stored state is f-tilde = f - dt/2 Omega - dt/2 S (Sec. II.B).
+ *
+ * Ownership: every state, field and output buffer is caller-owned device
+ * memory; the library never allocates or frees it.  A context owns only
+ * its small metric/coefficient tables and the per-launch scratch it
+ * documents below.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  Calls are asynchronous on that stream unless documented as
+ * synchronising.
+ *
+ * Errors: every int-returning call returns DUGKS_OK (0) or a negative code;
+ * the message of the last failure of a context is dugks_last_error(ctx),
+ * of a failed dugks_init is dugks_last_error(NULL).  Asynchronous HIP
+ * errors surface at the next synchronising call as DUGKS_EHIP.
+ *
+ * Threading: one context per host thread at a time; calls that overlap on
+ * one context race.
+ *
+ * Determinism: the forward path uses no atomics; results are bitwise
+ * reproducible from run to run on the same device.
+ */
+#ifndef DUGKS_H
+#define DUGKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DUGKS_OK 0
+#define DUGKS_EINVAL (-1)       /* invalid argument or configuration        */
+#define DUGKS_EUNSUPPORTED (-2) /* valid but not implemented for this case  */
+#define DUGKS_EHIP (-3)         /* HIP runtime error                        */
+#define DUGKS_ENONFINITE (-4)   /* moments found NaN/Inf in the state       */
+#define DUGKS_ENOMEM (-5)       /* device allocation of context tables      */
+
+enum dugks_lattice { DUGKS_D2Q9 = 9, DUGKS_D3Q19 = 19 };
+enum dugks_dtype { DUGKS_F32 = 0, DUGKS_F64 = 1 };
+enum dugks_mesh_kind { DUGKS_UNIFORM = 0, DUGKS_TANH = 1 };
+/* boundary kinds, one per domain side (-x,+x,-y,+y,-z,+z) */
+enum dugks_bc {
+    DUGKS_PERIODIC = 0,     /* both sides of the axis must be periodic      */
+    DUGKS_NEQ_VELOCITY = 1, /* Eq. (NEQ), velocity condition u_w           */
+    DUGKS_NEQ_PRESSURE = 2, /* Eq. (NEQ), pressure condition p_w           */
+    DUGKS_BOUNCE_BACK = 3   /* Eq. (BB), wall velocity u_w, rho_w = rho0    */
+};
+
+/*
+ * Problem description (Sec. II; mesh of Eq. Nonuniform_mesh).
+ *   n[3]        cells per axis (n[2] = 1 for D2Q9); wall axes need n >= 2
+ *   L[3]        domain length per axis
+ *   mesh[3]     DUGKS_UNIFORM or DUGKS_TANH per axis; faces of a tanh axis
+ *               are X_i = L (1/2 + tanh(k (i/N - 1/2)) / (2 tanh(k/2)))
+ *   rho0, RT    reference density, R T (c = sqrt(3 RT))
+ *   tau, dt     relaxation time and time step (both > 0)
+ *   G[3]        uniform part of the acceleration
+ *   omega,phase acceleration time factor g(t) = cos(omega t + phase):
+ *               G(x, t) = g(t) (G + G^(x)), G^ the optional force field
+ *   bc[6]       side kinds; uw[6][3] wall velocities; pw[6] wall pressures
+ *               (pressure p = (rho - rho0) RT)
+ */
+typedef struct {
+    int lattice;
+    int dtype;
+    int n[3];
+    double L[3];
+    int mesh[3];
+    double k_stretch;
+    double rho0, RT, tau, dt;
+    double G[3];
+    double omega, phase;
+    int bc[6];
+    double uw[6][3];
+    double pw[6];
+} dugks_config;
+
+typedef struct dugks_ctx dugks_ctx;
+typedef struct dugks_batch dugks_batch;
+
+/* Library version string. */
+const char* dugks_version(void);
+
+/* Message of the last failure on ctx (NULL: the last failed dugks_init /
+ * dugks_batch_create on this thread).  Never NULL. */
+const char* dugks_last_error(const dugks_ctx* ctx);
+
+/* dt = cfl * (smallest cell width) / sqrt(3 RT)  (Sec. III, CFL condition).
+ * Returns a negative value for an invalid configuration. */
+double dugks_dt_from_cfl(const dugks_config* cfg, double cfl);
+
+/*
+ * Create a context and write the initial state (Sec. III: "initialised by
+ * the equilibrium"): f~0 = feq(rho, u) - dt/2 S(rho, u, G(x, t0)) with the
+ * incompressible equilibrium of Eq. (icfeq) and S of Eq. (S), i.e. the
+ * state whose original distribution is the equilibrium.
+ *   rho    nullable scalar field (NULL: rho0 everywhere)
+ *   u      nullable vector field [D] (NULL: rest)
+ *   force  nullable force field G^ [D] (NULL: zero)
+ *   f_out  state buffer [Q] written on `stream`
+ *   out    receives the context; on failure *out = NULL and the error is
+ *          readable with dugks_last_error(NULL)
+ * t0 = 0.  The context owns device tables of O(n) size and, for the
+ * general kernels, one scratch state of (n+2)^D Q elements.
+ */
+int dugks_init(const dugks_config* cfg, const void* rho, const void* u, const void* force,
+               void* f_out, void* stream, dugks_ctx** out);
+
+/* Write the initial state of the context's configuration at time t0 again
+ * (same arguments as dugks_init). */
+int dugks_reset(dugks_ctx* ctx, const void* rho, const void* u, const void* force, double t0,
+                void* f_out, void* stream);
+
+/*
+ * One time step t_n -> t_n + dt of the Appendix algorithm (steps 1-9):
+ * f-bar-plus at the centres (Eq. f_bar_+), ghost extrapolation, interface
+ * reconstruction f-bar(x_b, t_n+h) = f-bar-plus(x_b) - xi h . grad
+ * (Eq. gradient), wall rules (Eqs. BB, NEQ), interface moments, original
+ * distribution at the interface (inverse of Eq. original_f), micro-flux
+ * (Eq. microflux) and the conservative update (Eqs. f_tilde_+,
+ * evolution_equation).
+ *   f_in, f_out  distinct state buffers [Q] (ping-pong; f_in == f_out is
+ *                DUGKS_EINVAL)
+ *   force        nullable force field G^ [D]
+ *   t_n          time of f_in (enters only through g(t))
+ * Asynchronous on `stream`.
+ */
+int dugks_step(dugks_ctx* ctx, const void* f_in, void* f_out, const void* force, double t_n,
+               void* stream);
+
+/* nsteps steps from f_a at time t0, ping-ponging between f_a and f_b;
+ * *which_out = 0 if the result is in f_a, 1 if in f_b.  Asynchronous. */
+int dugks_run(dugks_ctx* ctx, void* f_a, void* f_b, const void* force, double t0, int nsteps,
+              void* stream, int* which_out);
+
+/*
+ * Macroscopic fields at time t (Eq. macro_values; Appendix step 10):
+ *   rho = sum_q f~_q, u = sum_q xi_q f~_q / rho0 + dt/2 G(x, t),
+ *   p = (rho - rho0) RT.  rho, u [D], p are nullable device outputs.
+ * totals_host (nullable, 6 doubles, host memory): sum V rho, sum V j_x,
+ * sum V j_y, sum V j_z (j = sum xi f~), 1/2 sum V |u|^2, count of
+ * non-finite values in f.  With totals_host the call synchronises `stream`
+ * and returns DUGKS_ENONFINITE if the count is non-zero.  The reduction is
+ * deterministic (fixed-order two-pass, no atomics).
+ */
+int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, double t, void* rho, void* u,
+                  void* p, double* totals_host, void* stream);
+
+/*
+ * Reverse mode of one step on a fully periodic mesh (all sides
+ * DUGKS_PERIODIC; other cases return DUGKS_EUNSUPPORTED):
+ *   lam_n       = (d f_{n+1} / d f_n)^T lam_np1
+ *   grad_force += (d f_{n+1} / d G^)^T lam_np1   (nullable, [D])
+ * The forward intermediates are recomputed from f_n (no tape).  lam_n must
+ * not alias f_n or lam_np1.  Asynchronous.
+ */
+int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
+                       const void* lam_np1, void* lam_n, void* grad_force, void* stream);
+
+/*
+ * Reverse mode of the initial state with rho = rho0:
+ *   grad_u     += (d f0 / d u)^T lam0   (nullable, [D])
+ *   grad_force += (d f0 / d G^)^T lam0  (nullable, [D])
+ * at time t0.  Asynchronous.
+ */
+int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, const void* lam0,
+                   void* grad_u, void* grad_force, void* stream);
+
+/* Release the context and its device tables (synchronises its stream). */
+void dugks_destroy(dugks_ctx* ctx);
+
+/* ---------------------------------------------------------------------- */
+/* batched instances                                                       */
+/* ---------------------------------------------------------------------- */
+/*
+ * Many independent problems of uneven size, viscosity and forcing advanced
+ * by one kernel launch per step.
+ *   cfgs[n]     configurations (same lattice and dtype for all)
+ *   offsets[n]  element offset of instance i's state inside the packed
+ *               state buffer (each instance's Q planes are contiguous at
+ *               that offset, in the single-instance layout)
+ * The batch owns an instance table and its metric tables.
+ */
+int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t* offsets, void* stream,
+                       dugks_batch** out);
+
+/* Initial state of every instance (rest at rho0, zero force field). */
+int dugks_batch_init(dugks_batch* b, void* f_out, void* stream);
+
+/*
+ * nsteps steps of every instance from f_in (time t0 for all).  Steps
+ * ping-pong between f_in and f_out; after an odd nsteps the result is in
+ * f_out, after an even nsteps in f_in (*which_out = 1 or 0).  Instance i
+ * uses force field forces + force_offsets[i] when forces is non-NULL
+ * (force_offsets nullable = no field).  With use_graph != 0 the launches
+ * are captured once into a hipGraph and replayed.
+ */
+int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
+                    const int64_t* force_offsets, double t0, int nsteps, int use_graph, void* stream,
+                    int* which_out);
+
+void dugks_batch_destroy(dugks_batch* b);
+const char* dugks_batch_last_error(const dugks_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,270 @@
+"""MI355X (gfx950) incompressible DUGKS with body force (arXiv:1411.6121).
+
+Thin ctypes binding of ``libdugks.so`` (see ``include/dugks.h``).  The names
+``dugks_init``, ``dugks_step``, ... mirror the C entry points one to one and
+only marshal arguments: every stage of the step runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: without the built library every call raises.
+
+Configurations are plain dicts (keys as in ``dugks_config``)::
+
+    lattice 9|19, dtype "f32"|"f64", n (3), L (3), mesh (3), k_stretch,
+    rho0, RT, tau, dt, G (3), omega, phase, bc (6), uw (6x3), pw (6)
+
+Tensors: state ``[Q, nz, ny, nx]``, vector fields ``[D, nz, ny, nx]``,
+scalars ``[nz, ny, nx]``, all contiguous on the CUDA (HIP) device, in the
+configuration's dtype.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdugks.so")
+
+PERIODIC, NEQ_VELOCITY, NEQ_PRESSURE, BOUNCE_BACK = 0, 1, 2, 3
+UNIFORM, TANH = 0, 1
+OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ENOMEM = 0, -1, -2, -3, -4, -5
+
+
+class DugksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dugks error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int),
+        ("dtype", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("L", ctypes.c_double * 3),
+        ("mesh", ctypes.c_int * 3),
+        ("k_stretch", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("RT", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("G", ctypes.c_double * 3),
+        ("omega", ctypes.c_double),
+        ("phase", ctypes.c_double),
+        ("bc", ctypes.c_int * 6),
+        ("uw", (ctypes.c_double * 3) * 6),
+        ("pw", ctypes.c_double * 6),
+    ]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libdugks.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_1411_6121_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    CP = ctypes.POINTER(Config)
+    D = ctypes.c_double
+    I = ctypes.c_int
+    lib.dugks_version.restype = ctypes.c_char_p
+    lib.dugks_last_error.restype = ctypes.c_char_p
+    lib.dugks_last_error.argtypes = [_VP]
+    lib.dugks_dt_from_cfl.restype = D
+    lib.dugks_dt_from_cfl.argtypes = [CP, D]
+    lib.dugks_init.argtypes = [CP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_VP)]
+    lib.dugks_reset.argtypes = [_VP, _VP, _VP, _VP, D, _VP, _VP]
+    lib.dugks_step.argtypes = [_VP, _VP, _VP, _VP, D, _VP]
+    lib.dugks_run.argtypes = [_VP, _VP, _VP, _VP, D, I, _VP, ctypes.POINTER(I)]
+    lib.dugks_moments.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, ctypes.POINTER(D), _VP]
+    lib.dugks_step_adjoint.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
+    lib.dugks_init_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
+    lib.dugks_destroy.argtypes = [_VP]
+    lib.dugks_destroy.restype = None
+    lib.dugks_batch_create.argtypes = [CP, I, ctypes.POINTER(ctypes.c_int64), _VP, ctypes.POINTER(_VP)]
+    lib.dugks_batch_init.argtypes = [_VP, _VP, _VP]
+    lib.dugks_batch_run.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), D, I, I, _VP,
+                                    ctypes.POINTER(I)]
+    lib.dugks_batch_destroy.argtypes = [_VP]
+    lib.dugks_batch_destroy.restype = None
+    lib.dugks_batch_last_error.restype = ctypes.c_char_p
+    lib.dugks_batch_last_error.argtypes = [_VP]
+    _lib = lib
+    return lib
+
+
+def config(d: dict) -> Config:
+    c = Config()
+    c.lattice = int(d["lattice"])
+    dt = d.get("dtype", "f64")
+    c.dtype = 1 if dt in ("f64", "float64", 1) else 0
+    for a in range(3):
+        c.n[a] = int(d["n"][a])
+        c.L[a] = float(d["L"][a])
+        c.mesh[a] = int(d.get("mesh", (0, 0, 0))[a])
+        c.G[a] = float(d.get("G", (0.0, 0.0, 0.0))[a])
+    c.k_stretch = float(d.get("k_stretch", 0.0))
+    c.rho0 = float(d["rho0"])
+    c.RT = float(d["RT"])
+    c.tau = float(d["tau"])
+    c.dt = float(d["dt"])
+    c.omega = float(d.get("omega", 0.0))
+    c.phase = float(d.get("phase", 0.0))
+    uw = d.get("uw", [[0.0] * 3] * 6)
+    pw = d.get("pw", [0.0] * 6)
+    for s in range(6):
+        c.bc[s] = int(d["bc"][s])
+        c.pw[s] = float(pw[s])
+        for a in range(3):
+            c.uw[s][a] = float(uw[s][a])
+    return c
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc, ctx=None):
+    if rc != OK:
+        msg = load().dugks_last_error(ctx)
+        raise DugksError(rc, msg.decode() if msg else "")
+
+
+def version() -> str:
+    return load().dugks_version().decode()
+
+
+def dugks_dt_from_cfl(cfg: dict, cfl: float) -> float:
+    v = load().dugks_dt_from_cfl(ctypes.byref(config(cfg)), float(cfl))
+    if v < 0:
+        raise DugksError(EINVAL, "invalid configuration")
+    return v
+
+
+def dugks_init(cfg: dict, f_out, rho=None, u=None, force=None, stream=None):
+    """returns an opaque context handle (int); writes f~0 into f_out"""
+    lib = load()
+    h = ctypes.c_void_p()
+    rc = lib.dugks_init(ctypes.byref(config(cfg)), _ptr(rho), _ptr(u), _ptr(force), _ptr(f_out), _stream(stream),
+                        ctypes.byref(h))
+    _check(rc, None)
+    return h.value
+
+
+def dugks_reset(ctx, f_out, rho=None, u=None, force=None, t0=0.0, stream=None):
+    _check(load().dugks_reset(_VP(ctx), _ptr(rho), _ptr(u), _ptr(force), float(t0), _ptr(f_out),
+                              _stream(stream)), _VP(ctx))
+
+
+def dugks_step(ctx, f_in, f_out, force=None, t_n=0.0, stream=None):
+    _check(load().dugks_step(_VP(ctx), _ptr(f_in), _ptr(f_out), _ptr(force), float(t_n), _stream(stream)),
+           _VP(ctx))
+
+
+def dugks_run(ctx, f_a, f_b, nsteps, force=None, t0=0.0, stream=None) -> int:
+    which = ctypes.c_int(0)
+    _check(load().dugks_run(_VP(ctx), _ptr(f_a), _ptr(f_b), _ptr(force), float(t0), int(nsteps), _stream(stream),
+                            ctypes.byref(which)), _VP(ctx))
+    return which.value
+
+
+def dugks_moments(ctx, f, force=None, t=0.0, rho=None, u=None, p=None, totals=True, stream=None):
+    """fills the given output tensors; returns the 6 totals (synchronises) or None"""
+    tot = (ctypes.c_double * 6)() if totals else None
+    rc = load().dugks_moments(_VP(ctx), _ptr(f), _ptr(force), float(t), _ptr(rho), _ptr(u), _ptr(p),
+                              tot, _stream(stream))
+    _check(rc, _VP(ctx))
+    return list(tot) if totals else None
+
+
+def dugks_step_adjoint(ctx, f_n, lam_np1, lam_n, force=None, t_n=0.0, grad_force=None, stream=None):
+    _check(load().dugks_step_adjoint(_VP(ctx), _ptr(f_n), _ptr(force), float(t_n), _ptr(lam_np1), _ptr(lam_n),
+                                     _ptr(grad_force), _stream(stream)), _VP(ctx))
+
+
+def dugks_init_vjp(ctx, lam0, u=None, force=None, t0=0.0, grad_u=None, grad_force=None, stream=None):
+    _check(load().dugks_init_vjp(_VP(ctx), _ptr(u), _ptr(force), float(t0), _ptr(lam0), _ptr(grad_u),
+                                 _ptr(grad_force), _stream(stream)), _VP(ctx))
+
+
+def dugks_destroy(ctx):
+    if ctx:
+        load().dugks_destroy(_VP(ctx))
+
+
+def shape_of(cfg: dict):
+    """(Q, D, (nz, ny, nx)) of a configuration dict"""
+    Q = int(cfg["lattice"])
+    D = 2 if Q == 9 else 3
+    n = cfg["n"]
+    return Q, D, (int(n[2]), int(n[1]), int(n[0]))
+
+
+def torch_dtype(cfg: dict):
+    import torch
+
+    return torch.float64 if cfg.get("dtype", "f64") in ("f64", "float64", 1) else torch.float32
+
+
+class Solver:
+    """Owns a context and a ping-pong pair of state tensors on one device."""
+
+    def __init__(self, cfg: dict, rho=None, u=None, force=None, device="cuda"):
+        import torch
+
+        self.cfg = dict(cfg)
+        self.Q, self.D, self.shape = shape_of(cfg)
+        self.dtype = torch_dtype(cfg)
+        self.device = torch.device(device)
+        self.f = torch.empty((self.Q,) + self.shape, dtype=self.dtype, device=self.device)
+        self.g = torch.empty_like(self.f)
+        self.force = force
+        self.t = 0.0
+        self.ctx = dugks_init(self.cfg, self.f, rho, u, force)
+
+    def step(self, nsteps: int = 1):
+        which = dugks_run(self.ctx, self.f, self.g, nsteps, self.force, self.t)
+        if which:
+            self.f, self.g = self.g, self.f
+        self.t += nsteps * float(self.cfg["dt"])
+        return self.f
+
+    def moments(self, totals=True):
+        import torch
+
+        rho = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        u = torch.empty((self.D,) + self.shape, dtype=self.dtype, device=self.device)
+        p = torch.empty_like(rho)
+        tot = dugks_moments(self.ctx, self.f, self.force, self.t, rho, u, p, totals)
+        return rho, u, p, tot
+
+    def close(self):
+        if self.ctx:
+            dugks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,38 @@
+// ctx.hpp -- the context object behind the opaque dugks_ctx handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/dugks.h"
+#include "inst.hpp"
+
+struct dugks_ctx {
+    dugks_config cfg;
+    int D = 0, Q = 0, esize = 0;
+    long long nc = 0, ne = 0;
+    void* met = nullptr;          // metric tables (device)
+    void* phi = nullptr;          // f-bar-plus scratch of the general kernels (device, lazily)
+    double* partial = nullptr;    // per-block partial totals (device)
+    double* totals_dev = nullptr; // reduced totals (device)
+    int nblk_mom = 0;
+    dugks::Inst<float> pf;
+    dugks::Inst<double> pd;
+    std::string err;
+    int fast = 0;                 // fused-kernel variant selected at init (0 = none)
+    void* adj = nullptr;          // adjoint scratch (device, lazily)
+    size_t adj_bytes = 0;
+};
+
+namespace dugks {
+int fail(dugks_ctx* ctx, int code, const std::string& msg);
+int hip_check(dugks_ctx* ctx, hipError_t e, const char* what);
+int validate(const dugks_config* c, std::string& why);
+// fused single-launch step for the configurations it supports
+int setup_fast(dugks_ctx* ctx);
+int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st,
+              bool* handled);
+void release_fast(dugks_ctx* ctx);
+void release_adjoint(dugks_ctx* ctx);
+}  // namespace dugks

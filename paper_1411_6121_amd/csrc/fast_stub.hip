@@ -1,0 +1,19 @@
+// placeholder until the fused kernel lands
+#include "ctx.hpp"
+namespace dugks {
+int setup_fast(dugks_ctx* ctx) { ctx->fast = 0; return DUGKS_OK; }
+int fast_step(dugks_ctx*, const void*, void*, const void*, double, hipStream_t, bool* handled) { *handled = false; return DUGKS_OK; }
+void release_fast(dugks_ctx*) {}
+void release_adjoint(dugks_ctx*) {}
+}
+extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void*, const void*, double, const void*, void*, void*, void*)
+{ return dugks::fail(ctx, DUGKS_EUNSUPPORTED, "adjoint not built yet"); }
+extern "C" int dugks_init_vjp(dugks_ctx* ctx, const void*, const void*, double, const void*, void*, void*, void*)
+{ return dugks::fail(ctx, DUGKS_EUNSUPPORTED, "adjoint not built yet"); }
+extern "C" int dugks_batch_create(const dugks_config*, int, const int64_t*, void*, dugks_batch** out)
+{ if (out) *out = nullptr; return DUGKS_EUNSUPPORTED; }
+extern "C" int dugks_batch_init(dugks_batch*, void*, void*) { return DUGKS_EUNSUPPORTED; }
+extern "C" int dugks_batch_run(dugks_batch*, void*, void*, const void*, const int64_t*, double, int, int, void*, int*)
+{ return DUGKS_EUNSUPPORTED; }
+extern "C" void dugks_batch_destroy(dugks_batch*) {}
+extern "C" const char* dugks_batch_last_error(const dugks_batch*) { return "batch not built yet"; }

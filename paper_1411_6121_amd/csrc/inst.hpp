@@ -1,0 +1,102 @@
+// inst.hpp -- per-problem parameters seen by the kernels, and the
+// point-local formulas of the scheme (Sec. II) as device functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace dugks {
+
+enum { BC_PERIODIC = 0, BC_NEQ_VELOCITY = 1, BC_NEQ_PRESSURE = 2, BC_BOUNCE_BACK = 3 };
+
+// Metric table of one axis with n cells, element type T, stored back to back
+// in device memory:
+//   w  [n+1]  face f between cells f-1 and f: weight of the right cell in the
+//             linear interpolation to the face
+//   gn [n+1]  face f: 1/(x_f - x_{f-1})   (normal difference)
+//   cp [n], c0 [n], cm [n]
+//             cell-centred tangential derivative along this axis:
+//             d(i) = cp phi(i+1) + c0 phi(i) + cm phi(i-1); it is the difference
+//             of the interpolated values on the two faces of cell i over its
+//             width, so the tangential gradient on a face of another axis is
+//             (1-w) d(L) + w d(R), the bilinear cross-point difference
+//   fdx[n]    dt / Delta_i   (micro-flux scale, s_j/|V| = 1/Delta)
+//   dl [n]    Delta_i        (cell width)
+// Periodic axes use the wrapped, L-shifted neighbour centres and w[n] = w[0],
+// gn[n] = gn[0].  Wall axes use mirrored ghost centres.
+template <typename T>
+struct AxisMetric {
+    const T* w;
+    const T* gn;
+    const T* cp;
+    const T* c0;
+    const T* cm;
+    const T* fdx;
+    const T* dl;
+};
+
+template <typename T>
+struct Inst {
+    int n[3];      // cells per axis (1 on the absent z of 2-D)
+    int E[3];      // extended extent n+2 on active axes, 1 otherwise
+    int per[3];    // periodic flag (1 on the absent axis)
+    int bc[6];
+    long long nc;  // interior cells
+    long long ne;  // extended cells (with one ghost layer on active axes)
+    long long off; // element offset of this instance's state (batched)
+    long long foff;// element offset of its force field, -1 = none (batched)
+    long long poff;// element offset of its f-bar-plus scratch (batched)
+    T rho0, RT, c, h, dt;
+    T B1, C1;      // Eq. (f_bar_+) in deviation form: phi = f + B1 (feq - f) + C1 S
+    T B7, C7;      // step 7:  f = fbar + B7 (feq - fbar) + C7 S
+    T G0[3];
+    T uw[6][3];
+    T rhow[6];     // rho0 + p_w / RT (pressure condition)
+    T rlo[3], rhi[3]; // ghost(-1) = (1-rlo) phi(0) + rlo phi(1); ghost(n) likewise
+    double omega, phase;
+    AxisMetric<T> m[3];
+};
+
+template <typename T>
+__host__ __device__ inline T tfac(const Inst<T>& P, double t)
+{
+    return (T)cos(P.omega * t + P.phase);
+}
+
+// Eq. (icfeq): incompressible equilibrium, xi.u = c (e.u)
+template <class LAT, typename T>
+__device__ __forceinline__ T feq_q(int q, T rho, const T* u, T rho0, T c, T invRT)
+{
+    T eu = T(0), uu = T(0);
+#pragma unroll
+    for (int a = 0; a < LAT::D; ++a) {
+        if (LAT::e(q, a) == 1) eu += u[a];
+        if (LAT::e(q, a) == -1) eu -= u[a];
+        uu += u[a] * u[a];
+    }
+    const T xu = c * eu;
+    return T(LAT::w(q)) * (rho + rho0 * invRT * (xu + T(0.5) * xu * xu * invRT - T(0.5) * uu));
+}
+
+// Eq. (S) with the incompressible equilibrium: G.(xi - u)/RT feq
+template <class LAT, typename T>
+__device__ __forceinline__ T src_fac(int q, const T* u, const T* G, T c, T invRT)
+{
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < LAT::D; ++a) {
+        const int e = LAT::e(q, a);
+        s += G[a] * ((e == 0 ? T(0) : (e > 0 ? c : -c)) - u[a]);
+    }
+    return s * invRT;
+}
+
+template <class LAT, typename T>
+__device__ __forceinline__ T xi_of(int q, int a, T c)
+{
+    const int e = LAT::e(q, a);
+    return e == 0 ? T(0) : (e > 0 ? c : -c);
+}
+
+}  // namespace dugks
