@@ -87,6 +87,7 @@ def load():
     lib.dugks_moments.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, ctypes.POINTER(D), _VP]
     lib.dugks_step_adjoint.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_init_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
+    lib.dugks_kernel_variant.argtypes = [_VP]
     lib.dugks_destroy.argtypes = [_VP]
     lib.dugks_destroy.restype = None
     lib.dugks_batch_create.argtypes = [CP, I, ctypes.POINTER(ctypes.c_int64), _VP, ctypes.POINTER(_VP)]
@@ -205,6 +206,10 @@ def dugks_step_adjoint(ctx, f_n, lam_np1, lam_n, force=None, t_n=0.0, grad_force
 def dugks_init_vjp(ctx, lam0, u=None, force=None, t0=0.0, grad_u=None, grad_force=None, stream=None):
     _check(load().dugks_init_vjp(_VP(ctx), _ptr(u), _ptr(force), float(t0), _ptr(lam0), _ptr(grad_u),
                                  _ptr(grad_force), _stream(stream)), _VP(ctx))
+
+
+def dugks_kernel_variant(ctx) -> int:
+    return int(load().dugks_kernel_variant(_VP(ctx)))
 
 
 def dugks_destroy(ctx):

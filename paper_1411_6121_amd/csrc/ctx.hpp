@@ -13,6 +13,7 @@ struct dugks_ctx {
     int D = 0, Q = 0, esize = 0;
     long long nc = 0, ne = 0;
     void* met = nullptr;          // metric tables (device)
+    void* inst_dev = nullptr;     // device copy of the instance parameters
     void* phi = nullptr;          // f-bar-plus scratch of the general kernels (device, lazily)
     double* partial = nullptr;    // per-block partial totals (device)
     double* totals_dev = nullptr; // reduced totals (device)

@@ -246,27 +246,30 @@ extern "C" double dugks_dt_from_cfl(const dugks_config* cfg, double cfl)
 namespace dugks {
 
 template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_phi_one(Inst<T> P, const T* __restrict__ f, const T* __restrict__ force,
+__global__ __launch_bounds__(256) void k_phi_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                  T* __restrict__ phi, T gt)
 {
+    const Inst<T>& P = *Pp;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P.ne) return;
     phi_ext_body<LAT, T>(P, e, f, force, phi, gt);
 }
 
 template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_update_one(Inst<T> P, const T* __restrict__ f, const T* __restrict__ force,
+__global__ __launch_bounds__(256) void k_update_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                     const T* __restrict__ phi, T* __restrict__ fout, T gth)
 {
+    const Inst<T>& P = *Pp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nc) return;
     update_body<LAT, T>(P, c, f, force, phi, fout, gth);
 }
 
 template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_init_one(Inst<T> P, const T* rho, const T* u, const T* force, T gt,
+__global__ __launch_bounds__(256) void k_init_one(const Inst<T>* __restrict__ Pp, const T* rho, const T* u, const T* force, T gt,
                                                   T* fout)
 {
+    const Inst<T>& P = *Pp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nc) return;
     init_body<LAT, T>(P, c, rho, u, force, gt, fout);
@@ -274,10 +277,11 @@ __global__ __launch_bounds__(256) void k_init_one(Inst<T> P, const T* rho, const
 
 // macroscopic fields and per-block partial totals (Appendix step 10)
 template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_moments_one(Inst<T> P, const T* __restrict__ f, const T* __restrict__ force,
+__global__ __launch_bounds__(256) void k_moments_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                      T gt, T* rho_o, T* u_o, T* p_o, double* partial)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
     __shared__ double sh[6][256];
     const long long ci = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double loc[6] = {0, 0, 0, 0, 0, 0};
@@ -353,10 +357,10 @@ int launch_step_general(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
                         double t, hipStream_t st)
 {
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
-    hipLaunchKernelGGL((k_phi_one<LAT, T>), dim3(nblocks(P.ne, 256)), dim3(256), 0, st, P, (const T*)fin,
-                       (const T*)force, (T*)ctx->phi, gt);
-    hipLaunchKernelGGL((k_update_one<LAT, T>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, P, (const T*)fin,
-                       (const T*)force, (const T*)ctx->phi, (T*)fout, gth);
+    hipLaunchKernelGGL((k_phi_one<LAT, T>), dim3(nblocks(P.ne, 256)), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
+                       (const T*)fin, (const T*)force, (T*)ctx->phi, gt);
+    hipLaunchKernelGGL((k_update_one<LAT, T>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
+                       (const T*)fin, (const T*)force, (const T*)ctx->phi, (T*)fout, gth);
     return hip_check(ctx, hipGetLastError(), "step launch");
 }
 
@@ -364,7 +368,7 @@ template <class LAT, typename T>
 int launch_init(dugks_ctx* ctx, const Inst<T>& P, const void* rho, const void* u, const void* force, double t0,
                 void* fout, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_init_one<LAT, T>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, P, (const T*)rho,
+    hipLaunchKernelGGL((k_init_one<LAT, T>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev, (const T*)rho,
                        (const T*)u, (const T*)force, tfac(P, t0), (T*)fout);
     return hip_check(ctx, hipGetLastError(), "init launch");
 }
@@ -374,7 +378,8 @@ int launch_moments(dugks_ctx* ctx, const Inst<T>& P, const void* f, const void* 
                    void* u, void* p, hipStream_t st)
 {
     const unsigned nb = nblocks(P.nc, 256);
-    hipLaunchKernelGGL((k_moments_one<LAT, T>), dim3(nb), dim3(256), 0, st, P, (const T*)f, (const T*)force,
+    hipLaunchKernelGGL((k_moments_one<LAT, T>), dim3(nb), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev, (const T*)f,
+                       (const T*)force,
                        tfac(P, t), (T*)rho, (T*)u, (T*)p, ctx->partial);
     hipLaunchKernelGGL(k_reduce6, dim3(1), dim3(256), 0, st, (const double*)ctx->partial, (int)nb, ctx->totals_dev);
     return hip_check(ctx, hipGetLastError(), "moments launch");
@@ -423,6 +428,18 @@ extern "C" int dugks_init(const dugks_config* cfg, const void* rho, const void* 
         ctx->ne = ctx->pf.ne;
     }
     if (e != hipSuccess) { dugks_destroy(ctx); return fail(nullptr, DUGKS_EHIP, "metric upload failed"); }
+    {
+        const size_t isz = cfg->dtype == DUGKS_F64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
+        const void* src = cfg->dtype == DUGKS_F64 ? (const void*)&ctx->pd : (const void*)&ctx->pf;
+        if (hipMalloc(&ctx->inst_dev, isz) != hipSuccess) {
+            dugks_destroy(ctx);
+            return fail(nullptr, DUGKS_ENOMEM, "instance table allocation failed");
+        }
+        if (hipMemcpy(ctx->inst_dev, src, isz, hipMemcpyHostToDevice) != hipSuccess) {
+            dugks_destroy(ctx);
+            return fail(nullptr, DUGKS_EHIP, "instance table upload failed");
+        }
+    }
     ctx->nblk_mom = (int)((ctx->nc + 255) / 256);
     if (hipMalloc(&ctx->partial, (size_t)ctx->nblk_mom * 6 * sizeof(double)) != hipSuccess ||
         hipMalloc(&ctx->totals_dev, 8 * sizeof(double)) != hipSuccess) {
@@ -518,11 +535,14 @@ extern "C" int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, d
     return DUGKS_OK;
 }
 
+extern "C" int dugks_kernel_variant(const dugks_ctx* ctx) { return ctx ? ctx->fast : -1; }
+
 extern "C" void dugks_destroy(dugks_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
     if (ctx->met) (void)hipFree(ctx->met);
+    if (ctx->inst_dev) (void)hipFree(ctx->inst_dev);
     if (ctx->phi) (void)hipFree(ctx->phi);
     if (ctx->partial) (void)hipFree(ctx->partial);
     if (ctx->totals_dev) (void)hipFree(ctx->totals_dev);

@@ -1,0 +1,293 @@
+// kernels_fused.hip -- single-launch step for gfx950.
+//
+// One workgroup owns a halo-inclusive tile of columns in the plane of the
+// first D-1 axes (one thread per column) and marches along the last axis
+// (z in 3-D, y in 2-D) over a chunk of planes.  f-bar-plus (Appendix
+// steps 1-2) of three consecutive planes lives in an LDS ring; each new plane
+// is computed from the state once per column (ghost columns and ghost planes
+// by extrapolation inside LDS), and every interior thread then performs
+// steps 3-9 for its cell from LDS: the state is read once from HBM (plus the
+// tile halo, which hits L2) and the new state written once.
+//
+// Faces are evaluated by both neighbouring cells with identical code and
+// operands, so the two sides see bitwise-identical fluxes (conservation to
+// rounding).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ctx.hpp"
+#include "kernels_general.hpp"
+
+namespace dugks {
+
+// f-bar-plus in the LDS ring, relative to the thread's cell in the current
+// plane: ring slot offsets of the neighbouring planes are kept as integer
+// element offsets (dz_up, dz_dn), in-plane offsets are +-1 / +-BX.
+template <class LAT, typename T, int BX, int BY>
+struct LdsPhi {
+    const T* s;
+    int cur;           // element offset of (current plane, q = 0, this column)
+    int dz_up, dz_dn;  // offset from the current plane to the next / previous
+    static constexpr int SQ = BX * BY;  // stride between velocity planes
+    __device__ __forceinline__ int base(int ox, int oy, int oz) const
+    {
+        if constexpr (LAT::D == 3) return cur + ox + oy * BX + (oz > 0 ? dz_up : (oz < 0 ? dz_dn : 0));
+        else return cur + ox + (oy > 0 ? dz_up : (oy < 0 ? dz_dn : 0));
+    }
+    // offsets to the +t / -t neighbour of a cell in the current plane
+    __device__ __forceinline__ int up(int t) const
+    {
+        if constexpr (LAT::D == 3) return t == 0 ? 1 : (t == 1 ? BX : dz_up);
+        else return t == 0 ? 1 : dz_up;
+    }
+    __device__ __forceinline__ int dn(int t) const
+    {
+        if constexpr (LAT::D == 3) return t == 0 ? 1 : (t == 1 ? BX : -dz_dn);
+        else return t == 0 ? 1 : -dz_dn;
+    }
+    __device__ __forceinline__ T get(int q, int b) const { return s[b + q * SQ]; }
+};
+
+__device__ __forceinline__ int ring(int p) { return ((p % 3) + 3) % 3; }
+
+// metric coefficients of column coordinate x along in-plane axis a (clamped
+// for halo columns, which never update)
+template <typename T>
+__device__ __forceinline__ CellMetric<T> upd_col_pre(const Inst<T>& P, int a, int x)
+{
+    const int i = x < 0 ? 0 : (x >= P.n[a] ? P.n[a] - 1 : x);
+    return load_metric(P, a, i);
+}
+
+// kinds of a column coordinate along one in-plane axis
+enum { COL_CELL = 0, COL_GHOST_LO = 1, COL_GHOST_HI = 2, COL_OUT = 3 };
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+__global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
+                                                         const T* __restrict__ force, T* __restrict__ fout, T gt,
+                                                         T gth, int chunk, int tiles0)
+{
+    constexpr int Q = LAT::Q, D = LAT::D, M = D - 1;  // M: march axis
+    constexpr int NT = BX * BY;
+    const Inst<T>& P = *Pp;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int b0 = blockIdx.x % tiles0, b1 = blockIdx.x / tiles0;
+
+    // column coordinates (in-plane axes 0 .. D-2), kinds and source cells
+    int g[2], kind[2], src[2];
+    g[0] = b0 * (BX - 2) - 1 + tx;
+    g[1] = (D == 3) ? b1 * (BY - 2) - 1 + ty : 0;
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) {
+        const int N = P.n[a], x = g[a];
+        if (x >= 0 && x < N) { kind[a] = COL_CELL; src[a] = x; }
+        else if (P.per[a] && x == -1) { kind[a] = COL_CELL; src[a] = N - 1; }
+        else if (P.per[a] && x == N) { kind[a] = COL_CELL; src[a] = 0; }
+        else if (!P.per[a] && x == -1) { kind[a] = COL_GHOST_LO; src[a] = 0; }
+        else if (!P.per[a] && x == N) { kind[a] = COL_GHOST_HI; src[a] = N - 1; }
+        else { kind[a] = COL_OUT; src[a] = 0; }
+    }
+    if (D == 2) { kind[1] = COL_CELL; src[1] = 0; }
+    const bool cell_col = kind[0] == COL_CELL && kind[1] == COL_CELL;
+    const bool ghost_col = !cell_col && kind[0] != COL_OUT && kind[1] != COL_OUT;
+    const bool upd_col = cell_col && g[0] >= 0 && g[0] < P.n[0] && tx >= 1 && tx <= BX - 2 &&
+                         (D == 2 || (g[1] >= 0 && g[1] < P.n[1] && ty >= 1 && ty <= BY - 2));
+
+    const int nM = P.n[M];
+    const int p0 = blockIdx.y * chunk;
+    const int p1 = min(p0 + chunk, nM);
+    const bool perM = P.per[M] != 0;
+    // in-plane metric coefficients of this column are fixed for the march
+    const CellMetric<T> cmx = upd_col_pre(P, 0, g[0]);
+    const CellMetric<T> cmy = D == 3 ? upd_col_pre(P, 1, g[1]) : cmx;
+
+    auto slot_ptr = [&](int p, int q) -> T* {
+        return lds + ((long)(ring(p) * Q + q) * BY + ty) * BX + tx;
+    };
+    auto lds_at = [&](int p, int q, int dx, int dy) -> T {
+        return lds[((long)(ring(p) * Q + q) * BY + (ty + dy)) * BX + (tx + dx)];
+    };
+
+    // f-bar-plus of plane p (0 <= p < nM, or wrapped on a periodic march axis)
+    auto compute_plane = [&](int p) {
+        const int pp = perM ? ((p % nM) + nM) % nM : p;
+        if (cell_col) {
+            int c3[3];
+            c3[0] = src[0];
+            c3[1] = (D == 3) ? src[1] : pp;
+            c3[2] = (D == 3) ? pp : 0;
+            T v[Q];
+            phi_cell<LAT, T>(P, fin, force, int_idx(P, c3[0], c3[1], c3[2]), gt, v);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) slot_ptr(p, q)[0] = v[q];
+        }
+        __syncthreads();
+        if (ghost_col) {
+            // tensor-product extrapolation from the cells of the same plane
+            int off[2][2];
+            T wt[2][2];
+            int cnt[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                cnt[a] = 1;
+                off[a][0] = 0; wt[a][0] = T(1);
+                off[a][1] = 0; wt[a][1] = T(0);
+                if (a < D - 1 && kind[a] == COL_GHOST_LO) {
+                    cnt[a] = 2;
+                    off[a][0] = 1; wt[a][0] = T(1) - P.rlo[a];
+                    off[a][1] = 2; wt[a][1] = P.rlo[a];
+                } else if (a < D - 1 && kind[a] == COL_GHOST_HI) {
+                    cnt[a] = 2;
+                    off[a][0] = -1; wt[a][0] = T(1) - P.rhi[a];
+                    off[a][1] = -2; wt[a][1] = P.rhi[a];
+                }
+            }
+            T acc[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] = T(0);
+            for (int i1 = 0; i1 < cnt[1]; ++i1)
+                for (int i0 = 0; i0 < cnt[0]; ++i0) {
+                    const T w = wt[0][i0] * wt[1][i1];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) acc[q] += w * lds_at(p, q, off[0][i0], off[1][i1]);
+                }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) slot_ptr(p, q)[0] = acc[q];
+        }
+        __syncthreads();
+    };
+    // ghost plane p of a wall march axis: extrapolation along the march axis
+    // through planes a (nearest) and b, column by column
+    auto ghost_plane = [&](int p, int a, int b, T r) {
+        if (cell_col || ghost_col) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                slot_ptr(p, q)[0] = (T(1) - r) * slot_ptr(a, q)[0] + r * slot_ptr(b, q)[0];
+        }
+        __syncthreads();
+    };
+
+    int hi;
+    if (!perM && p0 == 0) {
+        compute_plane(0);
+        compute_plane(1);
+        ghost_plane(-1, 0, 1, P.rlo[M]);
+        hi = 1;
+    } else {
+        compute_plane(p0 - 1);
+        compute_plane(p0);
+        hi = p0;
+    }
+    for (int z = p0; z < p1; ++z) {
+        if (hi < z + 1) {
+            __syncthreads();  // the ring slot of z+1 held plane z-2, read by the last update
+            if (!perM && z + 1 == nM) ghost_plane(z + 1, z, z - 1, P.rhi[M]);
+            else compute_plane(z + 1);
+            hi = z + 1;
+        }
+        if (upd_col) {
+            int ci[3];
+            ci[0] = g[0];
+            ci[1] = (D == 3) ? g[1] : z;
+            ci[2] = (D == 3) ? z : 0;
+            const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+            const int slot = Q * BX * BY;
+            LdsPhi<LAT, T, BX, BY> ph{lds, ring(z) * slot + ty * BX + tx, (ring(z + 1) - ring(z)) * slot,
+                                      (ring(z - 1) - ring(z)) * slot};
+            T acc[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T p = ph.get(q, ph.cur);
+                acc[q] = p + (p - fin[(long long)q * P.nc + cidx]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
+            }
+            const CellMetric<T> cmm = load_metric(P, M, z);
+            if constexpr (D == 3) cell_fluxes<LAT, T>(P, ph, force, ci, gth, cmx, cmy, cmm, acc);
+            else cell_fluxes<LAT, T>(P, ph, force, ci, gth, cmx, cmm, cmm, acc);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fout[(long long)q * P.nc + cidx] = acc[q];
+        }
+    }
+    (void)NT;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+// device copy of the instance parameters of the context (uploaded at init)
+static const void* dev_inst(const dugks_ctx* ctx) { return ctx->inst_dev; }
+
+struct FusedShape {
+    int bx, by, chunk, tiles0, tiles1, chunks;
+    size_t lds;
+};
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
+                        hipStream_t st, int chunk)
+{
+    constexpr int D = LAT::D, M = D - 1;
+    const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
+    const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
+    const int chunks = (P.n[M] + chunk - 1) / chunk;
+    const size_t lds = (size_t)3 * LAT::Q * BX * BY * sizeof(T);
+    auto kern = k_fused<LAT, T, BX, BY, MINW>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_check(ctx, e, "fused kernel LDS attribute");
+        attr_set = true;
+    }
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
+    hipLaunchKernelGGL(kern, dim3(tiles0 * tiles1, chunks), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx), (const T*)fin,
+                       (const T*)force, (T*)fout, gt, gth, chunk, tiles0);
+    return hip_check(ctx, hipGetLastError(), "fused step launch");
+}
+
+// tile shapes: D3Q19 18x14 columns (16x12 interior), D2Q9 rows of 128
+// columns (126 interior); chunk = planes marched per workgroup
+static int pick_chunk(const dugks_ctx* ctx)
+{
+    const int D = ctx->D;
+    const int nM = ctx->cfg.n[D - 1];
+    long tiles;
+    if (D == 3) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 11) / 12);
+    else tiles = (ctx->cfg.n[0] + 125) / 126;
+    // aim for >= 4 workgroups per CU on 256 CUs, but march at least 8 planes
+    int chunk = 16;
+    while (chunk > 8 && tiles * ((nM + chunk - 1) / chunk) < 1024) chunk /= 2;
+    if (D == 2 && tiles * ((nM + chunk - 1) / chunk) < 1024) chunk = std::max(4, chunk / 2);
+    return std::min(chunk, std::max(nM, 1));
+}
+
+int setup_fast(dugks_ctx* ctx)
+{
+    ctx->fast = 0;
+    const char* env = getenv("DUGKS_FORCE_GENERAL");
+    if (env && env[0] == '1') return DUGKS_OK;
+    // the march axis needs two cells; in-plane axes are any size
+    ctx->fast = 1;
+    return DUGKS_OK;
+}
+
+int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, bool* handled)
+{
+    *handled = false;
+    if (ctx->fast != 1) return DUGKS_OK;
+    *handled = true;
+    const int chunk = pick_chunk(ctx);
+    if (ctx->cfg.lattice == DUGKS_D3Q19) {
+        if (ctx->cfg.dtype == DUGKS_F64) return launch_fused<D3Q19, double, 18, 14, 1>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+        return launch_fused<D3Q19, float, 18, 14, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+    }
+    if (ctx->cfg.dtype == DUGKS_F64) return launch_fused<D2Q9, double, 128, 1, 2>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+    return launch_fused<D2Q9, float, 128, 1, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+}
+
+void release_fast(dugks_ctx*) {}
+
+}  // namespace dugks

@@ -33,7 +33,7 @@ __device__ __forceinline__ long long int_idx(const Inst<T>& P, int i, int j, int
 
 // f-bar-plus of one interior cell (Appendix step 1)
 template <class LAT, typename T>
-__device__ void phi_cell(const Inst<T>& P, const T* __restrict__ f, const T* __restrict__ force, long long ci,
+__device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__ f, const T* __restrict__ force, long long ci,
                          T gt, T* out)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
@@ -65,7 +65,7 @@ __device__ void phi_cell(const Inst<T>& P, const T* __restrict__ f, const T* __r
 }
 
 template <class LAT, typename T>
-__device__ void phi_ext_body(const Inst<T>& P, long long e, const T* __restrict__ f, const T* __restrict__ force,
+__device__ __forceinline__ void phi_ext_body(const Inst<T>& P, long long e, const T* __restrict__ f, const T* __restrict__ force,
                              T* __restrict__ phi, T gt)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
@@ -119,38 +119,35 @@ __device__ void phi_ext_body(const Inst<T>& P, long long e, const T* __restrict_
     for (int q = 0; q < Q; ++q) phi[(long long)q * P.ne + e] = acc[q];
 }
 
+// run-time-axis selects of per-axis fields (no address of the by-value
+// kernel argument is taken, so it stays in scalar registers)
+#define SEL3(arr, a) ((a) == 0 ? (arr)[0] : ((a) == 1 ? (arr)[1] : (arr)[2]))
+
 // spatial force component d at the cell whose axis-a coordinate is x (which
 // may be a ghost), other coordinates from ci; ghosts follow the phi rule
 template <class LAT, typename T>
 __device__ __forceinline__ T force_at(const Inst<T>& P, const T* __restrict__ force, int d, int a, int x,
                                       const int* ci)
 {
-    if (!force) return T(0);
-    int cc[3] = {ci[0], ci[1], ci[2]};
-    const int N = P.n[a];
+    const int N = SEL3(P.n, a);
     const T* fd = force + (long long)d * P.nc;
-    if (x >= 0 && x < N) {
-        cc[a] = x;
-        return fd[int_idx(P, cc[0], cc[1], cc[2])];
-    }
-    if (P.per[a]) {
-        cc[a] = x < 0 ? N - 1 : 0;
-        return fd[int_idx(P, cc[0], cc[1], cc[2])];
-    }
-    const T r = x < 0 ? P.rlo[a] : P.rhi[a];
-    cc[a] = x < 0 ? 0 : N - 1;
-    const T v0 = fd[int_idx(P, cc[0], cc[1], cc[2])];
-    cc[a] = x < 0 ? 1 : N - 2;
-    const T v1 = fd[int_idx(P, cc[0], cc[1], cc[2])];
+    const long long sa = a == 0 ? 1LL : (a == 1 ? (long long)P.n[0] : (long long)P.n[0] * P.n[1]);
+    const int x0 = ci[0], y0 = ci[1], z0 = ci[2];
+    const long long c0 = int_idx(P, x0, y0, z0) - (long long)(a == 0 ? x0 : (a == 1 ? y0 : z0)) * sa;
+    if (x >= 0 && x < N) return fd[c0 + x * sa];
+    if (SEL3(P.per, a)) return fd[c0 + (x < 0 ? N - 1 : 0) * sa];
+    const T r = x < 0 ? SEL3(P.rlo, a) : SEL3(P.rhi, a);
+    const T v0 = fd[c0 + (x < 0 ? 0 : N - 1) * sa];
+    const T v1 = fd[c0 + (x < 0 ? 1 : N - 2) * sa];
     return (T(1) - r) * v0 + r * v1;
 }
 
-// acceleration on face f of axis a (between cells f-1 and f) at time factor gth
+// acceleration on face f of axis a (between cells f-1 and f) at time factor
+// gth; w = interpolation weight of the face
 template <class LAT, typename T>
-__device__ __forceinline__ void face_force(const Inst<T>& P, const T* __restrict__ force, int a, int f,
+__device__ __forceinline__ void face_force(const Inst<T>& P, const T* __restrict__ force, int a, int f, T w,
                                            const int* ci, T gth, T* G)
 {
-    const T w = P.m[a].w[f];
 #pragma unroll
     for (int d = 0; d < LAT::D; ++d) {
         T gh = T(0);
@@ -163,44 +160,99 @@ __device__ __forceinline__ void face_force(const Inst<T>& P, const T* __restrict
     }
 }
 
-// Appendix steps 3-4 on face f of axis a: the face value of f-bar-plus
-// (linear in the normal direction) minus h xi . grad, with the normal
-// gradient from the two cells and each tangential gradient from the two
-// cells' cell-centred derivatives (bilinear cross-point difference).
+// Accessor of f-bar-plus in the ghost-extended global array, relative to
+// the cell the thread updates: base(ox,oy,oz) gives the element offset of a
+// neighbour, up(t)/dn(t) the offset to its +t / -t neighbour, get(q, b) the
+// value of velocity q there.
 template <class LAT, typename T>
-__device__ void recon_face(const Inst<T>& P, const T* __restrict__ phi, int a, int f, const int* ci, T* out)
+struct GlobalPhi {
+    const T* __restrict__ phi;
+    long long ne, ie, s1, s2;
+    __device__ __forceinline__ long long base(int ox, int oy, int oz) const { return ie + ox + oy * s1 + oz * s2; }
+    __device__ __forceinline__ long long up(int t) const { return t == 0 ? 1 : (t == 1 ? s1 : s2); }
+    __device__ __forceinline__ long long dn(int t) const { return up(t); }
+    __device__ __forceinline__ T get(int q, long long b) const { return phi[(long long)q * ne + b]; }
+};
+
+// Metric coefficients one cell needs along one axis, held in registers:
+// interpolation weight and normal-difference scale of its two faces, its
+// cell-centred derivative coefficients and its flux scale dt/Delta.
+template <typename T>
+struct CellMetric {
+    T wl, wu, gl, gu, cp, c0, cm, fdx;
+};
+
+template <typename T>
+__device__ __forceinline__ CellMetric<T> load_metric(const Inst<T>& P, int a, int i)
+{
+    const AxisMetric<T>& m = P.m[a];
+    return CellMetric<T>{m.w[i], m.w[i + 1], m.gn[i], m.gn[i + 1], m.cp[i], m.c0[i], m.cm[i], m.fdx[i]};
+}
+
+template <typename T>
+__device__ __forceinline__ T pick1(T x, T y, T z, int a) { return a == 0 ? x : (a == 1 ? y : z); }
+
+template <typename T>
+__device__ __forceinline__ CellMetric<T> pick(const CellMetric<T> x, const CellMetric<T> y, const CellMetric<T> z,
+                                              int a)
+{
+    // register selects on values (never through an indexed array)
+    CellMetric<T> r;
+    r.wl = pick1(x.wl, y.wl, z.wl, a);
+    r.wu = pick1(x.wu, y.wu, z.wu, a);
+    r.gl = pick1(x.gl, y.gl, z.gl, a);
+    r.gu = pick1(x.gu, y.gu, z.gu, a);
+    r.cp = pick1(x.cp, y.cp, z.cp, a);
+    r.c0 = pick1(x.c0, y.c0, z.c0, a);
+    r.cm = pick1(x.cm, y.cm, z.cm, a);
+    r.fdx = pick1(x.fdx, y.fdx, z.fdx, a);
+    return r;
+}
+
+// e_{q,a} for a run-time axis a (q compile-time): a select of constants
+template <class LAT>
+__device__ __forceinline__ int e_rt(int q, int a)
+{
+    return a == 0 ? LAT::e(q, 0) : (a == 1 ? LAT::e(q, 1) : LAT::e(q, 2));
+}
+
+// Appendix steps 3-4 on the lower (upper = false) or upper face of the cell
+// along axis a: the face value of f-bar-plus (linear in the normal
+// direction) minus h xi . grad, with the normal gradient from the two cells
+// and each tangential gradient from the two cells' cell-centred derivatives
+// (= bilinear cross-point difference over the face width).
+template <class LAT, typename T, class ACC>
+__device__ __forceinline__ void recon_face(const Inst<T>& P, const ACC& ph, int a, bool upper,
+                                           const CellMetric<T>& ma, const CellMetric<T>& m1, int t1,
+                                           const CellMetric<T>& m2, int t2, T* out)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    int cl[3] = {ci[0], ci[1], ci[2]}, cr[3] = {ci[0], ci[1], ci[2]};
-    cl[a] = f - 1;
-    cr[a] = f;
-    const long long iL = ext_idx<LAT, T>(P, cl[0], cl[1], cl[2]);
-    const long long iR = ext_idx<LAT, T>(P, cr[0], cr[1], cr[2]);
-    const T w = P.m[a].w[f];
-    const T hg = P.h * P.m[a].gn[f];
-    long long st[3];
-    st[0] = 1;
-    st[1] = P.E[0];
-    st[2] = (long long)P.E[0] * P.E[1];
-    T cp[3], c0[3], cm[3];
-#pragma unroll
-    for (int t = 0; t < D; ++t) {
-        if (t == a) continue;
-        cp[t] = P.m[t].cp[ci[t]];
-        c0[t] = P.m[t].c0[ci[t]];
-        cm[t] = P.m[t].cm[ci[t]];
-    }
+    const int lo = upper ? 0 : -1;  // offset of the left cell along a
+    const auto bL = ph.base(a == 0 ? lo : 0, a == 1 ? lo : 0, a == 2 ? lo : 0);
+    const auto bR = ph.base(a == 0 ? lo + 1 : 0, a == 1 ? lo + 1 : 0, a == 2 ? lo + 1 : 0);
+    const auto u1 = ph.up(t1), d1 = ph.dn(t1);
+    const auto u2 = ph.up(t2), d2 = ph.dn(t2);
+    const T w = upper ? ma.wu : ma.wl;
+    const T hcg = P.h * P.c * (upper ? ma.gu : ma.gl);
+    const T hc = P.h * P.c;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T* pq = phi + (long long)q * P.ne;
-        const T pL = pq[iL], pR = pq[iR];
-        T v = pL + w * (pR - pL) - xi_of<LAT, T>(q, a, P.c) * hg * (pR - pL);
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-            if (t == a || LAT::e(q, t) == 0) continue;
-            const T dL = cp[t] * pq[iL + st[t]] + c0[t] * pL + cm[t] * pq[iL - st[t]];
-            const T dR = cp[t] * pq[iR + st[t]] + c0[t] * pR + cm[t] * pq[iR - st[t]];
-            v -= P.h * xi_of<LAT, T>(q, t, P.c) * (dL + w * (dR - dL));
+        const T pL = ph.get(q, bL), pR = ph.get(q, bR);
+        const int ea = e_rt<LAT>(q, a);
+        T v = pL + w * (pR - pL) - T(ea) * hcg * (pR - pL);
+        const int e1 = e_rt<LAT>(q, t1);
+        if (e1 != 0) {
+            const T dL = m1.cp * ph.get(q, bL + u1) + m1.c0 * pL + m1.cm * ph.get(q, bL - d1);
+            const T dR = m1.cp * ph.get(q, bR + u1) + m1.c0 * pR + m1.cm * ph.get(q, bR - d1);
+            v -= T(e1) * hc * (dL + w * (dR - dL));
+        }
+        if (D == 3) {
+            const int e2 = e_rt<LAT>(q, t2);
+            if (e2 != 0) {
+                const T dL = m2.cp * ph.get(q, bL + u2) + m2.c0 * pL + m2.cm * ph.get(q, bL - d2);
+                const T dR = m2.cp * ph.get(q, bR + u2) + m2.c0 * pR + m2.cm * ph.get(q, bR - d2);
+                v -= T(e2) * hc * (dL + w * (dR - dL));
+            }
         }
         out[q] = v;
     }
@@ -225,12 +277,32 @@ __device__ __forceinline__ void face_moments(const Inst<T>& P, const T* fb, cons
     for (int a = 0; a < LAT::D; ++a) u[a] = P.c * j[a] / P.rho0 + T(0.5) * P.h * G[a];
 }
 
-// Appendix step 5 on a wall face of side s.  wall: reconstructed values on
-// the wall face (modified in place for the velocities entering the domain);
-// oppf: reconstructed values on the opposite interface of the same wall
-// cell; Gopp: acceleration there.
+// What the NEQ rule needs from the opposite interface x_c of a wall cell:
+// its moments and, for the velocities crossing the axis, the
+// non-equilibrium part f-bar - feq(rho_c, u_c).
 template <class LAT, typename T>
-__device__ void wall_rule(const Inst<T>& P, int s, T* wall, const T* oppf, const T* Gopp)
+struct NeqInfo {
+    T rc, uc[3];
+    T neq[LAT::Q];
+};
+
+template <class LAT, typename T>
+__device__ __forceinline__ void neq_capture(const Inst<T>& P, int a, const T* oppf, const T* Gopp,
+                                            NeqInfo<LAT, T>& I)
+{
+    const T invRT = T(1) / P.RT;
+    face_moments<LAT, T>(P, oppf, Gopp, I.rc, I.uc);
+#pragma unroll
+    for (int q = 0; q < LAT::Q; ++q) {
+        if (LAT::e(q, a) == 0) continue;
+        I.neq[q] = oppf[q] - feq_q<LAT, T>(q, I.rc, I.uc, P.rho0, P.c, invRT);
+    }
+}
+
+// Appendix step 5 on a wall face of side s (Eqs. BB, NEQ), in place on the
+// reconstructed values, for the velocities entering the domain.
+template <class LAT, typename T>
+__device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, const NeqInfo<LAT, T>& I)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const int a = s >> 1;
@@ -248,23 +320,20 @@ __device__ void wall_rule(const Inst<T>& P, int s, T* wall, const T* oppf, const
         }
         return;
     }
-    T rc, uc[3];
-    face_moments<LAT, T>(P, oppf, Gopp, rc, uc);
     T ra, ua[3];
     if (kind == BC_NEQ_VELOCITY) {
-        ra = rc;
+        ra = I.rc;
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = P.uw[s][d];
     } else {
         ra = P.rhow[s];
 #pragma unroll
-        for (int d = 0; d < D; ++d) ua[d] = uc[d];
+        for (int d = 0; d < D; ++d) ua[d] = I.uc[d];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (LAT::e(q, a) * sg >= 0) continue;
-        wall[q] = feq_q<LAT, T>(q, ra, ua, P.rho0, P.c, invRT) +
-                  (oppf[q] - feq_q<LAT, T>(q, rc, uc, P.rho0, P.c, invRT));
+        wall[q] = feq_q<LAT, T>(q, ra, ua, P.rho0, P.c, invRT) + I.neq[q];
     }
 }
 
@@ -285,50 +354,189 @@ __device__ __forceinline__ void face_original(const Inst<T>& P, int a, T* fb, co
 }
 
 template <class LAT, typename T>
-__device__ void update_body(const Inst<T>& P, long long cidx, const T* __restrict__ f, const T* __restrict__ force,
-                            const T* __restrict__ phi, T* __restrict__ fout, T gth)
+__device__ __forceinline__ void neq_capture_rt(const Inst<T>& P, int a, const T* oppf, const T* Gopp,
+                                               NeqInfo<LAT, T>& I)
+{
+    const T invRT = T(1) / P.RT;
+    face_moments<LAT, T>(P, oppf, Gopp, I.rc, I.uc);
+#pragma unroll
+    for (int q = 0; q < LAT::Q; ++q) I.neq[q] = oppf[q] - feq_q<LAT, T>(q, I.rc, I.uc, P.rho0, P.c, invRT);
+}
+
+template <class LAT, typename T>
+__device__ __forceinline__ void wall_rule_rt(const Inst<T>& P, int s, int a, T* wall, const NeqInfo<LAT, T>& I)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
+    const int sg = (s & 1) ? 1 : -1;  // outward normal = sg e_a
+    const T invRT = T(1) / P.RT;
+    int kind = P.bc[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+        if (k == s) kind = P.bc[k];
+    T uws[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) uws[d] = P.uw[0][d];
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+        if (k == s)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) uws[d] = P.uw[k][d];
+    if (kind == BC_BOUNCE_BACK) {
+        T pre[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pre[q] = wall[q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (e_rt<LAT>(q, a) * sg >= 0) continue;
+            T xu = T(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) xu += xi_of<LAT, T>(q, d, P.c) * uws[d];
+            wall[q] = pre[LAT::opp(q)] + T(2) * P.rho0 * T(LAT::w(q)) * xu * invRT;
+        }
+        return;
+    }
+    T ra, ua[3];
+    if (kind == BC_NEQ_VELOCITY) {
+        ra = I.rc;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ua[d] = uws[d];
+    } else {
+        ra = P.rho0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (k == s) ra = P.rhow[k];
+#pragma unroll
+        for (int d = 0; d < D; ++d) ua[d] = I.uc[d];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (e_rt<LAT>(q, a) * sg >= 0) continue;
+        wall[q] = feq_q<LAT, T>(q, ra, ua, P.rho0, P.c, invRT) + I.neq[q];
+    }
+}
+
+template <class LAT, typename T>
+__device__ __forceinline__ void face_original_rt(const Inst<T>& P, int a, T* fb, const T* G)
+{
+    const T invRT = T(1) / P.RT;
+    T rho, u[3];
+    face_moments<LAT, T>(P, fb, G, rho, u);
+#pragma unroll
+    for (int q = 0; q < LAT::Q; ++q) {
+        if (e_rt<LAT>(q, a) == 0) continue;
+        const T fe = feq_q<LAT, T>(q, rho, u, P.rho0, P.c, invRT);
+        const T S = src_fac<LAT, T>(q, u, G, P.c, invRT) * fe;
+        fb[q] = fb[q] + P.B7 * (fe - fb[q]) + P.C7 * S;
+    }
+}
+
+// Appendix steps 3-4, compile-time axis A, run-time side (see recon_face)
+template <class LAT, typename T, class ACC, int A>
+__device__ __forceinline__ void recon_face_ct(const Inst<T>& P, const ACC& ph, bool upper, const CellMetric<T>& ma,
+                                              const CellMetric<T>& mx, const CellMetric<T>& my,
+                                              const CellMetric<T>& mz, T* out)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const int lo = upper ? 0 : -1;
+    const auto bL = ph.base(A == 0 ? lo : 0, A == 1 ? lo : 0, A == 2 ? lo : 0);
+    const auto bR = ph.base(A == 0 ? lo + 1 : 0, A == 1 ? lo + 1 : 0, A == 2 ? lo + 1 : 0);
+    const T w = upper ? ma.wu : ma.wl;
+    const T hcg = P.h * P.c * (upper ? ma.gu : ma.gl);
+    const T hc = P.h * P.c;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const T pL = ph.get(q, bL), pR = ph.get(q, bR);
+        T v = pL + w * (pR - pL) - T(LAT::e(q, A)) * hcg * (pR - pL);
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            if (t == A || LAT::e(q, t) == 0) continue;
+            const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
+            const auto u = ph.up(t), d = ph.dn(t);
+            const T dL = mt.cp * ph.get(q, bL + u) + mt.c0 * pL + mt.cm * ph.get(q, bL - d);
+            const T dR = mt.cp * ph.get(q, bR + u) + mt.c0 * pR + mt.cm * ph.get(q, bR - d);
+            v -= T(LAT::e(q, t)) * hc * (dL + w * (dR - dL));
+        }
+        out[q] = v;
+    }
+}
+
+template <class LAT, typename T, class ACC, int A>
+__device__ __forceinline__ void axis_fluxes_ct(const Inst<T>& P, const ACC& ph, const T* __restrict__ force,
+                                               const int* ci, T gth, const CellMetric<T>& mx,
+                                               const CellMetric<T>& my, const CellMetric<T>& mz, T* acc)
+{
+    constexpr int Q = LAT::Q;
+    const CellMetric<T>& ma = A == 0 ? mx : (A == 1 ? my : mz);
+    const int ca = ci[A];
+    const bool wlo = !P.per[A] && ca == 0;
+    const bool whi = !P.per[A] && ca == P.n[A] - 1;
+    NeqInfo<LAT, T> info;
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {
+        // k = 0: the face that is not a wall of this cell (upper face if the
+        // lower one is a wall), k = 1: the other one
+        const bool upper = wlo ? (k == 0) : (k == 1);
+        asm volatile("" ::: "memory");
+        T fb[Q], G[3];
+        recon_face_ct<LAT, T, ACC, A>(P, ph, upper, ma, mx, my, mz, fb);
+        face_force<LAT, T>(P, force, A, upper ? ca + 1 : ca, upper ? ma.wu : ma.wl, ci, gth, G);
+        const bool wall_here = upper ? whi : wlo;
+        if (k == 0 && (wlo != whi)) neq_capture<LAT, T>(P, A, fb, G, info);
+        if (wall_here) wall_rule<LAT, T>(P, upper ? 2 * A + 1 : 2 * A, fb, info);
+        face_original<LAT, T>(P, A, fb, G);
+        const T s = ma.fdx * P.c;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (LAT::e(q, A) == 0) continue;
+            // upper face: outward normal +e_A; lower face: -e_A
+            const T fl = (upper ? fb[q] : -fb[q]) * s;
+            acc[q] = (LAT::e(q, A) > 0) ? acc[q] - fl : acc[q] + fl;
+        }
+    }
+}
+
+// Steps 3-9 for one cell: acc holds f~+ on entry (Eq. f_tilde_+) and the
+// updated state on exit.  Faces are taken one at a time; on a wall axis the
+// opposite (interior) face is evaluated first so that the NEQ rule can use
+// its moments and non-equilibrium part.
+template <class LAT, typename T, class ACC>
+__device__ __forceinline__ void cell_fluxes(const Inst<T>& P, const ACC& ph, const T* __restrict__ force,
+                                            const int* ci, T gth, const CellMetric<T> cx, const CellMetric<T> cy,
+                                            const CellMetric<T> cz, T* acc)
+{
+    axis_fluxes_ct<LAT, T, ACC, 0>(P, ph, force, ci, gth, cx, cy, cz, acc);
+    axis_fluxes_ct<LAT, T, ACC, 1>(P, ph, force, ci, gth, cx, cy, cz, acc);
+    if constexpr (LAT::D == 3) axis_fluxes_ct<LAT, T, ACC, 2>(P, ph, force, ci, gth, cx, cy, cz, acc);
+}
+
+template <class LAT, typename T>
+__device__ __forceinline__ void update_body(const Inst<T>& P, long long cidx, const T* __restrict__ f, const T* __restrict__ force,
+                            const T* __restrict__ phi, T* __restrict__ fout, T gth)
+{
+    constexpr int Q = LAT::Q;
     int ci[3];
     ci[0] = (int)(cidx % P.n[0]);
     long long r = cidx / P.n[0];
     ci[1] = (int)(r % P.n[1]);
     ci[2] = (int)(r / P.n[1]);
-    const long long ie = ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]);
+    GlobalPhi<LAT, T> ph{phi, P.ne, ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]), (long long)P.E[0],
+                         (long long)P.E[0] * P.E[1]};
     T acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T p = phi[(long long)q * P.ne + ie];
+        const T p = ph.get(q, ph.base(0, 0, 0));
         acc[q] = p + (p - f[(long long)q * P.nc + cidx]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
     }
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        T fm[Q], fp[Q], Gm[3], Gp[3];
-        const int fmi = ci[a], fpi = ci[a] + 1;
-        recon_face<LAT, T>(P, phi, a, fmi, ci, fm);
-        recon_face<LAT, T>(P, phi, a, fpi, ci, fp);
-        face_force<LAT, T>(P, force, a, fmi, ci, gth, Gm);
-        face_force<LAT, T>(P, force, a, fpi, ci, gth, Gp);
-        if (!P.per[a]) {
-            if (ci[a] == 0) wall_rule<LAT, T>(P, 2 * a, fm, fp, Gp);
-            if (ci[a] == P.n[a] - 1) wall_rule<LAT, T>(P, 2 * a + 1, fp, fm, Gm);
-        }
-        face_original<LAT, T>(P, a, fm, Gm);
-        face_original<LAT, T>(P, a, fp, Gp);
-        const T s = P.m[a].fdx[ci[a]];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (LAT::e(q, a) == 0) continue;
-            const T flux = (fp[q] - fm[q]) * s;
-            acc[q] = (LAT::e(q, a) > 0) ? acc[q] - P.c * flux : acc[q] + P.c * flux;
-        }
-    }
+    const CellMetric<T> cx = load_metric(P, 0, ci[0]);
+    const CellMetric<T> cy = load_metric(P, 1, ci[1]);
+    const CellMetric<T> cz = LAT::D == 3 ? load_metric(P, 2, ci[2]) : cy;
+    cell_fluxes<LAT, T>(P, ph, force, ci, gth, cx, cy, cz, acc);
 #pragma unroll
     for (int q = 0; q < Q; ++q) fout[(long long)q * P.nc + cidx] = acc[q];
 }
 
 template <class LAT, typename T>
-__device__ void init_body(const Inst<T>& P, long long ci, const T* rho, const T* u, const T* force, T gt,
+__device__ __forceinline__ void init_body(const Inst<T>& P, long long ci, const T* rho, const T* u, const T* force, T gt,
                           T* fout)
 {
     constexpr int Q = LAT::Q, D = LAT::D;

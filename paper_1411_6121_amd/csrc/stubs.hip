@@ -1,9 +1,6 @@
-// placeholder until the fused kernel lands
+// entry points not built yet
 #include "ctx.hpp"
 namespace dugks {
-int setup_fast(dugks_ctx* ctx) { ctx->fast = 0; return DUGKS_OK; }
-int fast_step(dugks_ctx*, const void*, void*, const void*, double, hipStream_t, bool* handled) { *handled = false; return DUGKS_OK; }
-void release_fast(dugks_ctx*) {}
 void release_adjoint(dugks_ctx*) {}
 }
 extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void*, const void*, double, const void*, void*, void*, void*)

@@ -34,10 +34,26 @@ def to_dev(a, cfg):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=tdt(cfg))
 
 
-def gpu_run(cfg, f0, nsteps, force=None, t0=0.0):
+def make_ctx(cfg, fb, variant=None, **kw):
+    """context on the requested step kernel (None: library default = fused)"""
+    import os
+    old = os.environ.get("DUGKS_FORCE_GENERAL")
+    os.environ["DUGKS_FORCE_GENERAL"] = "1" if variant == "general" else "0"
+    try:
+        ctx = M.dugks_init(cfg, fb, **kw)
+    finally:
+        if old is None:
+            del os.environ["DUGKS_FORCE_GENERAL"]
+        else:
+            os.environ["DUGKS_FORCE_GENERAL"] = old
+    assert M.dugks_kernel_variant(ctx) == (0 if variant == "general" else 1)
+    return ctx
+
+
+def gpu_run(cfg, f0, nsteps, force=None, t0=0.0, variant=None):
     fa = to_dev(f0, cfg)
     fb = torch.empty_like(fa)
-    ctx = M.dugks_init(cfg, fb)
+    ctx = make_ctx(cfg, fb, variant)
     try:
         which = M.dugks_run(ctx, fa, fb, nsteps, to_dev(force, cfg), t0)
         torch.cuda.synchronize()
@@ -82,6 +98,9 @@ CASES = [
                                                                        [0.05, 0, 0], [0, 0, 0], [0, 0, 0]],
        pw=[0, 0, 1e-3, 0, 0, 0], G=(1e-4, 2e-4, 0), force_field=True, mesh=(0, 1, 0), k_stretch=1.0, dt=0.3),
     c2("d2q9-minimal", (1, 2), (0, 0, 1, 1, 0, 0), uw=LID),
+    c2("d2q9-wide-tiles", (300, 21), (1, 1, 0, 0, 0, 0), uw=[[0, 0.01, 0], [0, -0.01, 0]] + [[0, 0, 0]] * 4,
+       G=(0, 1e-4, 0)),
+    c3("d3q19-multi-tile", (40, 30, 20), (3, 3, 1, 1, 0, 0), uw=LID3, G=(0, 0, 1e-4)),
     c3("d3q19-periodic-force", (13, 11, 9), (0,) * 6, G=(1e-4, 0, -2e-4), omega=0.1, force_field=True),
     c3("d3q19-cavity-neq", (17, 15, 13), (1,) * 6, uw=LID3),
     c3("d3q19-cavity-neq-tanh", (16, 19, 14), (1,) * 6, uw=LID3, mesh=(1, 1, 1), k_stretch=1.5, dt=0.25),
@@ -99,17 +118,18 @@ def case_force(cfg, seed):
     return field(seed, (D,) + shp, 1e-4)
 
 
+@pytest.mark.parametrize("variant", ["fused", "general"])
 @pytest.mark.parametrize("cfg", CASES, ids=[c["name"] for c in CASES])
-def test_step_parity_f64(cfg):
-    say(f"[parity f64] {cfg['name']} n={cfg['n']}")
+def test_step_parity_f64(cfg, variant):
+    say(f"[parity f64] {cfg['name']} n={cfg['n']} {variant}")
     force = case_force(cfg, 5)
     f0 = start_state(cfg, 11, force)
     t0 = 0.7
     ref1 = O.step(cfg, f0, force, t0)
-    got1 = gpu_run(cfg, f0, 1, force, t0)
+    got1 = gpu_run(cfg, f0, 1, force, t0, variant)
     assert rel_linf(got1, ref1) < 1e-12
     ref = O.run(cfg, f0, 30, force, t0)
-    got = gpu_run(cfg, f0, 30, force, t0)
+    got = gpu_run(cfg, f0, 30, force, t0, variant)
     assert rel_linf(got, ref) < 1e-11
 
 
