@@ -194,6 +194,16 @@ int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, 
  * 1 = fused single-launch kernel (diagnostics). */
 int dugks_kernel_variant(const dugks_ctx* ctx);
 
+/*
+ * Reverse mode of the read-out of dugks_moments at time t:
+ *   lam[q]      = grad_rho + xi_q . grad_u / rho0     (overwritten, [Q])
+ *   grad_force += g(t) dt/2 grad_u                      (nullable, [D])
+ * grad_rho (scalar field) and grad_u ([D]) are nullable (= zero).
+ * Asynchronous.
+ */
+int dugks_moments_vjp(dugks_ctx* ctx, const void* grad_rho, const void* grad_u, double t, void* lam,
+                      void* grad_force, void* stream);
+
 /* Release the context and its device tables (synchronises its stream). */
 void dugks_destroy(dugks_ctx* ctx);
 

@@ -87,6 +87,7 @@ def load():
     lib.dugks_moments.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, ctypes.POINTER(D), _VP]
     lib.dugks_step_adjoint.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_init_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
+    lib.dugks_moments_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP]
     lib.dugks_kernel_variant.argtypes = [_VP]
     lib.dugks_destroy.argtypes = [_VP]
     lib.dugks_destroy.restype = None
@@ -206,6 +207,11 @@ def dugks_step_adjoint(ctx, f_n, lam_np1, lam_n, force=None, t_n=0.0, grad_force
 def dugks_init_vjp(ctx, lam0, u=None, force=None, t0=0.0, grad_u=None, grad_force=None, stream=None):
     _check(load().dugks_init_vjp(_VP(ctx), _ptr(u), _ptr(force), float(t0), _ptr(lam0), _ptr(grad_u),
                                  _ptr(grad_force), _stream(stream)), _VP(ctx))
+
+
+def dugks_moments_vjp(ctx, lam, grad_rho=None, grad_u=None, t=0.0, grad_force=None, stream=None):
+    _check(load().dugks_moments_vjp(_VP(ctx), _ptr(grad_rho), _ptr(grad_u), float(t), _ptr(lam), _ptr(grad_force),
+                                    _stream(stream)), _VP(ctx))
 
 
 def dugks_kernel_variant(ctx) -> int:

@@ -1,12 +1,5 @@
 // entry points not built yet
 #include "ctx.hpp"
-namespace dugks {
-void release_adjoint(dugks_ctx*) {}
-}
-extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void*, const void*, double, const void*, void*, void*, void*)
-{ return dugks::fail(ctx, DUGKS_EUNSUPPORTED, "adjoint not built yet"); }
-extern "C" int dugks_init_vjp(dugks_ctx* ctx, const void*, const void*, double, const void*, void*, void*, void*)
-{ return dugks::fail(ctx, DUGKS_EUNSUPPORTED, "adjoint not built yet"); }
 extern "C" int dugks_batch_create(const dugks_config*, int, const int64_t*, void*, dugks_batch** out)
 { if (out) *out = nullptr; return DUGKS_EUNSUPPORTED; }
 extern "C" int dugks_batch_init(dugks_batch*, void*, void*) { return DUGKS_EUNSUPPORTED; }
