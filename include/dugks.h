@@ -222,22 +222,31 @@ void dugks_destroy(dugks_ctx* ctx);
 int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t* offsets, void* stream,
                        dugks_batch** out);
 
-/* Initial state of every instance (rest at rho0, zero force field). */
+/* Initial state of every instance at time 0: the equilibrium at rest at
+ * rho0 under its uniform acceleration G (force fields enter from the first
+ * step); resets the batch clock. */
 int dugks_batch_init(dugks_batch* b, void* f_out, void* stream);
 
 /*
- * nsteps steps of every instance from f_in (time t0 for all).  Steps
- * ping-pong between f_in and f_out; after an odd nsteps the result is in
- * f_out, after an even nsteps in f_in (*which_out = 1 or 0).  Instance i
- * uses force field forces + force_offsets[i] when forces is non-NULL
- * (force_offsets nullable = no field).  With use_graph != 0 the launches
- * are captured once into a hipGraph and replayed.
+ * nsteps steps of every instance from f_in.  Steps ping-pong between f_in
+ * and f_out; after an odd nsteps the result is in f_out, after an even
+ * nsteps in f_in (*which_out = 1 or 0).  The batch keeps a device-side step
+ * counter s (0 after dugks_batch_init, +nsteps per run): instance i is at
+ * time s dt_i, so time-dependent forcing stays correct across runs.
+ * Instance i uses the force field forces + force_offsets[i] when forces is
+ * non-NULL and force_offsets[i] >= 0 (force_offsets nullable = no fields).
+ * With use_graph != 0 the launches are captured once into a hipGraph (per
+ * buffer pair, force buffer and nsteps) and replayed; this needs a
+ * non-default stream.  Asynchronous.
  */
 int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
-                    const int64_t* force_offsets, double t0, int nsteps, int use_graph, void* stream,
+                    const int64_t* force_offsets, int nsteps, int use_graph, void* stream,
                     int* which_out);
 
 void dugks_batch_destroy(dugks_batch* b);
+
+/* Message of the last failure on b (NULL: the last failed
+ * dugks_batch_create on this thread).  Never NULL. */
 const char* dugks_batch_last_error(const dugks_batch* b);
 
 #ifdef __cplusplus

@@ -93,7 +93,7 @@ def load():
     lib.dugks_destroy.restype = None
     lib.dugks_batch_create.argtypes = [CP, I, ctypes.POINTER(ctypes.c_int64), _VP, ctypes.POINTER(_VP)]
     lib.dugks_batch_init.argtypes = [_VP, _VP, _VP]
-    lib.dugks_batch_run.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), D, I, I, _VP,
+    lib.dugks_batch_run.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), I, I, _VP,
                                     ctypes.POINTER(I)]
     lib.dugks_batch_destroy.argtypes = [_VP]
     lib.dugks_batch_destroy.restype = None
@@ -273,6 +273,115 @@ class Solver:
         if self.ctx:
             dugks_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _align(n, a):
+    return (n + a - 1) // a * a
+
+
+class BatchSolver:
+    """Many independent instances (same lattice and dtype) advanced together:
+    one kernel launch per step for all of them, optionally replayed from a
+    captured hipGraph.  State of instance i: ``solver.state(i)``."""
+
+    def __init__(self, cfgs, device="cuda", forces=None):
+        import torch
+
+        if not cfgs:
+            raise ValueError("need at least one instance")
+        self.cfgs = [dict(c) for c in cfgs]
+        self.dtype = torch_dtype(self.cfgs[0])
+        esize = 8 if self.dtype == torch.float64 else 4
+        per = 256 // esize  # 256-byte aligned instance offsets
+        self.offsets, self.shapes = [], []
+        tot = 0
+        for c in self.cfgs:
+            Q, D, shp = shape_of(c)
+            self.offsets.append(tot)
+            self.shapes.append((Q,) + shp)
+            tot += _align(Q * shp[0] * shp[1] * shp[2], per)
+        self.total = tot
+        self.device = torch.device(device)
+        self.f = torch.empty(tot, dtype=self.dtype, device=self.device)
+        self.g = torch.empty_like(self.f)
+        n = len(self.cfgs)
+        arr = (Config * n)(*[config(c) for c in self.cfgs])
+        offs = (ctypes.c_int64 * n)(*self.offsets)
+        h = ctypes.c_void_p()
+        lib = load()
+        rc = lib.dugks_batch_create(arr, n, offs, _stream(None), ctypes.byref(h))
+        if rc != OK:
+            raise DugksError(rc, lib.dugks_batch_last_error(None).decode())
+        self.h = h.value
+        self.forces, self.force_offsets = None, None
+        if forces is not None:
+            self.set_forces(forces)
+        self._check(lib.dugks_batch_init(_VP(self.h), _ptr(self.f), _stream(None)))
+        self.steps = 0
+        self._graph_stream = None
+
+    def _check(self, rc):
+        if rc != OK:
+            raise DugksError(rc, load().dugks_batch_last_error(_VP(self.h)).decode())
+
+    def set_forces(self, forces):
+        """forces: list (per instance) of [D, nz, ny, nx] tensors or None"""
+        import torch
+
+        esize = 8 if self.dtype == torch.float64 else 4
+        per = 256 // esize
+        offs, tot = [], 0
+        for fr in forces:
+            offs.append(tot if fr is not None else -1)
+            if fr is not None:
+                tot += _align(fr.numel(), per)
+        buf = torch.zeros(max(tot, 1), dtype=self.dtype, device=self.device)
+        for fr, o in zip(forces, offs):
+            if fr is not None:
+                buf[o:o + fr.numel()] = fr.reshape(-1)
+        self.forces = buf
+        self.force_offsets = (ctypes.c_int64 * len(offs))(*offs)
+
+    def state(self, i):
+        o = self.offsets[i]
+        Q, nz, ny, nx = self.shapes[i]
+        return self.f[o:o + Q * nz * ny * nx].view(Q, nz, ny, nx)
+
+    def run(self, nsteps, use_graph=False):
+        import torch
+
+        which = ctypes.c_int(0)
+        lib = load()
+        if use_graph:
+            if self._graph_stream is None:
+                self._graph_stream = torch.cuda.Stream(device=self.device)
+            cur = torch.cuda.current_stream(self.device)
+            self._graph_stream.wait_stream(cur)
+            with torch.cuda.stream(self._graph_stream):
+                self._check(lib.dugks_batch_run(_VP(self.h), _ptr(self.f), _ptr(self.g), _ptr(self.forces),
+                                                self.force_offsets, int(nsteps), 1,
+                                                ctypes.c_void_p(self._graph_stream.cuda_stream),
+                                                ctypes.byref(which)))
+            cur.wait_stream(self._graph_stream)
+        else:
+            self._check(lib.dugks_batch_run(_VP(self.h), _ptr(self.f), _ptr(self.g), _ptr(self.forces),
+                                            self.force_offsets, int(nsteps), 0, _stream(None),
+                                            ctypes.byref(which)))
+        if which.value:
+            self.f, self.g = self.g, self.f
+        self.steps += int(nsteps)
+        return self.f
+
+    def close(self):
+        if self.h:
+            load().dugks_batch_destroy(_VP(self.h))
+            self.h = None
 
     def __del__(self):
         try:

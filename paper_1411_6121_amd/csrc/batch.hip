@@ -1,0 +1,283 @@
+// batch.hip -- many independent problems of uneven size, viscosity and
+// forcing, advanced by one launch of the fused kernel per step (block table
+// maps each workgroup to its instance, tile and march chunk); the step
+// launches of a run can be captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+#include "kernels_general.hpp"
+
+namespace dugks {
+hipError_t batch_step_launch(int lattice, int dtype, const void* insts, const long long* bstart, const BatchGeom* geom,
+                             int n, long long nblocks, const void* fin, const void* forces, void* fout,
+                             const long long* step0, int step, hipStream_t st);
+
+// batch clock: set / advance the device-side step counter (kernel nodes, so
+// a captured run replays them)
+__global__ void k_batch_clock(long long* s, long long add, int reset)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *s = reset ? 0 : *s + add;
+}
+void fused_tile_shape(int lattice, int* bx, int* by);
+
+// initial state of every instance: rest at rho0 (Sec. III), t = t0
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_batch_init(const Inst<T>* __restrict__ insts,
+                                                    const long long* __restrict__ cstart, int ninst, double t0,
+                                                    T* __restrict__ f)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cstart[ninst]) return;
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    const Inst<T>& P = insts[lo];
+    init_body<LAT, T>(P, c - cstart[lo], nullptr, nullptr, nullptr, tfac(P, t0), f + P.off);
+}
+}  // namespace dugks
+
+using namespace dugks;
+
+struct dugks_batch {
+    int n = 0, lattice = 0, dtype = 0, D = 0, Q = 0, esize = 0;
+    int bx = 0, by = 0;
+    std::vector<dugks_config> cfgs;
+    std::vector<unsigned char> hinst;  // host images of Inst<T>, n of them
+    void* insts_dev = nullptr;
+    void* met_dev = nullptr;
+    long long* bstart_dev = nullptr;
+    long long* cstart_dev = nullptr;
+    long long* step_dev = nullptr;  // device step counter (batch clock)
+    BatchGeom* geom_dev = nullptr;
+    long long nblocks = 0, ncells = 0;
+    size_t lds = 0;
+    std::string err = "no error";
+    // captured run
+    hipGraphExec_t gexec = nullptr;
+    const void* g_in = nullptr;
+    void* g_out = nullptr;
+    const void* g_forces = nullptr;
+    int g_steps = -1;
+    hipStream_t g_stream = nullptr;
+};
+
+static thread_local std::string g_batch_err = "no error";
+
+static int bfail(dugks_batch* b, int code, const std::string& m)
+{
+    if (b) b->err = m;
+    else g_batch_err = m;
+    return code;
+}
+
+namespace dugks {
+template <typename T>
+void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& met_host);
+size_t metric_len(const dugks_config* c);
+}  // namespace dugks
+
+template <typename T>
+static int build_tables(dugks_batch* b, const int64_t* offsets, hipStream_t st)
+{
+    const int n = b->n;
+    size_t mtot = 0;
+    for (int i = 0; i < n; ++i) mtot += metric_len(&b->cfgs[i]);
+    if (hipMalloc(&b->met_dev, mtot * sizeof(T)) != hipSuccess) return bfail(b, DUGKS_ENOMEM, "metric allocation");
+    std::vector<T> mall;
+    mall.reserve(mtot);
+    std::vector<Inst<T>> insts(n);
+    std::vector<long long> bstart(n + 1, 0), cstart(n + 1, 0);
+    std::vector<BatchGeom> geom(n);
+    size_t moff = 0;
+    for (int i = 0; i < n; ++i) {
+        std::vector<T> mh;
+        fill_inst<T>(&b->cfgs[i], insts[i], (T*)b->met_dev + moff, mh);
+        moff += mh.size();
+        mall.insert(mall.end(), mh.begin(), mh.end());
+        insts[i].off = offsets[i];
+        insts[i].foff = -1;
+        const int D = b->D, M = D - 1;
+        BatchGeom g;
+        g.tiles0 = (insts[i].n[0] + b->bx - 3) / (b->bx - 2);
+        g.tiles1 = D == 3 ? (insts[i].n[1] + b->by - 3) / (b->by - 2) : 1;
+        g.chunk = D == 3 ? 16 : 8;
+        g.pad = 0;
+        const int chunks = (insts[i].n[M] + g.chunk - 1) / g.chunk;
+        geom[i] = g;
+        bstart[i + 1] = bstart[i] + (long long)g.tiles0 * g.tiles1 * chunks;
+        cstart[i + 1] = cstart[i] + insts[i].nc;
+    }
+    b->nblocks = bstart[n];
+    b->ncells = cstart[n];
+    b->hinst.resize(sizeof(Inst<T>) * n);
+    std::memcpy(b->hinst.data(), insts.data(), b->hinst.size());
+    if (hipMalloc(&b->insts_dev, b->hinst.size()) != hipSuccess ||
+        hipMalloc((void**)&b->bstart_dev, sizeof(long long) * (n + 1)) != hipSuccess ||
+        hipMalloc((void**)&b->cstart_dev, sizeof(long long) * (n + 1)) != hipSuccess ||
+        hipMalloc((void**)&b->geom_dev, sizeof(BatchGeom) * n) != hipSuccess ||
+        hipMalloc((void**)&b->step_dev, sizeof(long long)) != hipSuccess)
+        return bfail(b, DUGKS_ENOMEM, "batch table allocation");
+    if (hipMemcpy(b->met_dev, mall.data(), mall.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->insts_dev, b->hinst.data(), b->hinst.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->bstart_dev, bstart.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->cstart_dev, cstart.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->geom_dev, geom.data(), sizeof(BatchGeom) * n, hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, DUGKS_EHIP, "batch table upload");
+    (void)st;
+    return DUGKS_OK;
+}
+
+extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t* offsets, void* stream,
+                                  dugks_batch** out)
+{
+    if (!out) return bfail(nullptr, DUGKS_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!cfgs || !offsets || n < 1) return bfail(nullptr, DUGKS_EINVAL, "need at least one instance and offsets");
+    for (int i = 0; i < n; ++i) {
+        std::string why;
+        if (validate(&cfgs[i], why) != DUGKS_OK) return bfail(nullptr, DUGKS_EINVAL, "instance " + std::to_string(i) + ": " + why);
+        if (cfgs[i].lattice != cfgs[0].lattice || cfgs[i].dtype != cfgs[0].dtype)
+            return bfail(nullptr, DUGKS_EINVAL, "all instances must share lattice and dtype");
+        if (offsets[i] < 0) return bfail(nullptr, DUGKS_EINVAL, "negative offset");
+    }
+    dugks_batch* b = new dugks_batch();
+    b->n = n;
+    b->lattice = cfgs[0].lattice;
+    b->dtype = cfgs[0].dtype;
+    b->D = b->lattice == DUGKS_D2Q9 ? 2 : 3;
+    b->Q = b->lattice;
+    b->esize = b->dtype == DUGKS_F64 ? 8 : 4;
+    fused_tile_shape(b->lattice, &b->bx, &b->by);
+    b->lds = (size_t)3 * b->Q * b->bx * b->by * b->esize;
+    b->cfgs.assign(cfgs, cfgs + n);
+    const int rc = b->dtype == DUGKS_F64 ? build_tables<double>(b, offsets, (hipStream_t)stream)
+                                         : build_tables<float>(b, offsets, (hipStream_t)stream);
+    if (rc != DUGKS_OK) {
+        g_batch_err = b->err;
+        dugks_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return DUGKS_OK;
+}
+
+template <class LAT, typename T>
+static int batch_init_t(dugks_batch* b, void* f, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_batch_init<LAT, T>), dim3((unsigned)((b->ncells + 255) / 256)), dim3(256), 0, st,
+                       (const Inst<T>*)b->insts_dev, (const long long*)b->cstart_dev, b->n, 0.0, (T*)f);
+    hipLaunchKernelGGL(k_batch_clock, dim3(1), dim3(1), 0, st, b->step_dev, 0LL, 1);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EHIP, hipGetErrorString(e));
+}
+
+extern "C" int dugks_batch_init(dugks_batch* b, void* f_out, void* stream)
+{
+    if (!b) return bfail(nullptr, DUGKS_EINVAL, "null batch");
+    if (!f_out) return bfail(b, DUGKS_EINVAL, "null state buffer");
+    const hipStream_t st = (hipStream_t)stream;
+    if (b->lattice == DUGKS_D2Q9)
+        return b->dtype == DUGKS_F64 ? batch_init_t<D2Q9, double>(b, f_out, st) : batch_init_t<D2Q9, float>(b, f_out, st);
+    return b->dtype == DUGKS_F64 ? batch_init_t<D3Q19, double>(b, f_out, st) : batch_init_t<D3Q19, float>(b, f_out, st);
+}
+
+static int batch_launch_any(dugks_batch* b, const void* fin, void* fout, const void* forces, int step, hipStream_t st)
+{
+    const hipError_t e = batch_step_launch(b->lattice, b->dtype, b->insts_dev, b->bstart_dev, b->geom_dev, b->n,
+                                           b->nblocks, fin, forces, fout, b->step_dev, step, st);
+    return e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EHIP, hipGetErrorString(e));
+}
+
+static void drop_graph(dugks_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->g_steps = -1;
+}
+
+static int launch_run(dugks_batch* b, const void* f_in, void* f_out, const void* forces, int nsteps, hipStream_t st)
+{
+    const void* cur = f_in;
+    void* nxt = f_out;
+    for (int k = 0; k < nsteps; ++k) {
+        const int rc = batch_launch_any(b, cur, nxt, forces, k, st);
+        if (rc != DUGKS_OK) return rc;
+        void* tmp = const_cast<void*>(cur);
+        cur = nxt;
+        nxt = tmp;
+    }
+    hipLaunchKernelGGL(k_batch_clock, dim3(1), dim3(1), 0, st, b->step_dev, (long long)nsteps, 0);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EHIP, hipGetErrorString(e));
+}
+
+extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
+                               const int64_t* force_offsets, int nsteps, int use_graph, void* stream, int* which_out)
+{
+    if (!b) return bfail(nullptr, DUGKS_EINVAL, "null batch");
+    if (!f_in || !f_out || f_in == f_out) return bfail(b, DUGKS_EINVAL, "need two distinct state buffers");
+    if (nsteps < 0) return bfail(b, DUGKS_EINVAL, "negative step count");
+    const hipStream_t st = (hipStream_t)stream;
+    // per-instance force offsets (instance table update, before any launch)
+    bool changed = false;
+    const size_t isz = b->dtype == DUGKS_F64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
+    for (int i = 0; i < b->n; ++i) {
+        long long fo = (forces && force_offsets) ? (long long)force_offsets[i] : -1;
+        long long* slot = (long long*)(b->hinst.data() + i * isz +
+                                       (b->dtype == DUGKS_F64 ? offsetof(Inst<double>, foff) : offsetof(Inst<float>, foff)));
+        if (*slot != fo) { *slot = fo; changed = true; }
+    }
+    if (changed) {
+        drop_graph(b);
+        if (hipMemcpy(b->insts_dev, b->hinst.data(), b->hinst.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(b, DUGKS_EHIP, "instance table update");
+    }
+    if (use_graph) {
+        if (!st) return bfail(b, DUGKS_EINVAL, "graph capture needs a non-default stream");
+        if (!b->gexec || b->g_in != f_in || b->g_out != f_out || b->g_forces != forces || b->g_steps != nsteps ||
+            b->g_stream != st) {
+            drop_graph(b);
+            hipGraph_t graph = nullptr;
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return bfail(b, DUGKS_EHIP, "stream capture begin");
+            const int rc = launch_run(b, f_in, f_out, forces, nsteps, st);
+            const hipError_t ee = hipStreamEndCapture(st, &graph);
+            if (rc != DUGKS_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+            if (ee != hipSuccess) return bfail(b, DUGKS_EHIP, "stream capture end");
+            const hipError_t ie = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) { b->gexec = nullptr; return bfail(b, DUGKS_EHIP, "graph instantiate"); }
+            b->g_in = f_in; b->g_out = f_out; b->g_forces = forces; b->g_steps = nsteps; b->g_stream = st;
+        }
+        const hipError_t le = hipGraphLaunch(b->gexec, st);
+        if (le != hipSuccess) return bfail(b, DUGKS_EHIP, "graph launch");
+    } else {
+        const int rc = launch_run(b, f_in, f_out, forces, nsteps, st);
+        if (rc != DUGKS_OK) return rc;
+    }
+    if (which_out) *which_out = nsteps & 1;
+    return DUGKS_OK;
+}
+
+extern "C" void dugks_batch_destroy(dugks_batch* b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->insts_dev) (void)hipFree(b->insts_dev);
+    if (b->met_dev) (void)hipFree(b->met_dev);
+    if (b->bstart_dev) (void)hipFree(b->bstart_dev);
+    if (b->cstart_dev) (void)hipFree(b->cstart_dev);
+    if (b->geom_dev) (void)hipFree(b->geom_dev);
+    if (b->step_dev) (void)hipFree(b->step_dev);
+    delete b;
+}
+
+extern "C" const char* dugks_batch_last_error(const dugks_batch* b) { return b ? b->err.c_str() : g_batch_err.c_str(); }

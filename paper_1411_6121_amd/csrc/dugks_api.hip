@@ -199,6 +199,7 @@ void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& me
     }
     P.omega = c->omega;
     P.phase = c->phase;
+    P.dtd = c->dt;
     met_host.clear();
     for (int a = 0; a < D; ++a) {
         std::vector<double> m;

@@ -55,7 +55,13 @@ struct Inst {
     T rhow[6];     // rho0 + p_w / RT (pressure condition)
     T rlo[3], rhi[3]; // ghost(-1) = (1-rlo) phi(0) + rlo phi(1); ghost(n) likewise
     double omega, phase;
+    double dtd;    // dt in double (time stamps of the time factor)
     AxisMetric<T> m[3];
+};
+
+// per-instance launch geometry of the batched fused kernel
+struct BatchGeom {
+    int tiles0, tiles1, chunk, pad;
 };
 
 template <typename T>

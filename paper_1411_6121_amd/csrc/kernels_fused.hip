@@ -63,20 +63,18 @@ __device__ __forceinline__ CellMetric<T> upd_col_pre(const Inst<T>& P, int a, in
 // kinds of a column coordinate along one in-plane axis
 enum { COL_CELL = 0, COL_GHOST_LO = 1, COL_GHOST_HI = 2, COL_OUT = 3 };
 
-template <class LAT, typename T, int BX, int BY, int MINW>
-__global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
-                                                         const T* __restrict__ force, T* __restrict__ fout, T gt,
-                                                         T gth, int chunk, int tiles0)
+// One workgroup's work: tile index `tile` (of tiles0 x tiles1) and march
+// chunk `ck` of the instance P; fin/fout/force already point at the
+// instance's arrays.
+template <class LAT, typename T, int BX, int BY>
+__device__ __forceinline__ void fused_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
+                                           T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
+                                           int ck, T* lds)
 {
     constexpr int Q = LAT::Q, D = LAT::D, M = D - 1;  // M: march axis
-    constexpr int NT = BX * BY;
-    const Inst<T>& P = *Pp;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = tid / BX;
-    const int b0 = blockIdx.x % tiles0, b1 = blockIdx.x / tiles0;
+    const int b0 = tile % tiles0, b1 = tile / tiles0;
 
     // column coordinates (in-plane axes 0 .. D-2), kinds and source cells
     int g[2], kind[2], src[2];
@@ -99,7 +97,7 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restric
                          (D == 2 || (g[1] >= 0 && g[1] < P.n[1] && ty >= 1 && ty <= BY - 2));
 
     const int nM = P.n[M];
-    const int p0 = blockIdx.y * chunk;
+    const int p0 = ck * chunk;
     const int p1 = min(p0 + chunk, nM);
     const bool perM = P.per[M] != 0;
     // in-plane metric coefficients of this column are fixed for the march
@@ -212,7 +210,51 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restric
             for (int q = 0; q < Q; ++q) fout[(long long)q * P.nc + cidx] = acc[q];
         }
     }
-    (void)NT;
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+__global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
+                                                         const T* __restrict__ force, T* __restrict__ fout,
+                                                         double t, int chunk, int tiles0)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Inst<T>& P = *Pp;
+    // time factors evaluated on the device (same code as the batched form)
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
+    fused_body<LAT, T, BX, BY>(P, fin, force, fout, gt, gth, chunk, tiles0, blockIdx.x, blockIdx.y,
+                               reinterpret_cast<T*>(smem_raw));
+}
+
+// Batched form: block b belongs to the instance i with bstart[i] <= b <
+// bstart[i+1]; the instance table holds each instance's state offset, force
+// offset, tile counts and chunk (BatchGeom).  Time of instance i at this
+// launch: t0 + step * dt_i.
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+__global__ __launch_bounds__(BX* BY, MINW) void k_fused_batch(const Inst<T>* __restrict__ insts,
+                                                               const long long* __restrict__ bstart,
+                                                               const BatchGeom* __restrict__ geom, int ninst,
+                                                               const T* __restrict__ fin, const T* __restrict__ forces,
+                                                               T* __restrict__ fout,
+                                                               const long long* __restrict__ step0, int step)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const long long b = blockIdx.x;
+    int lo = 0, hi = ninst - 1;  // bstart[lo] <= b < bstart[hi+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bstart[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const Inst<T>& P = insts[lo];
+    const BatchGeom g = geom[lo];
+    const int local = (int)(b - bstart[lo]);
+    const int ntile = g.tiles0 * g.tiles1;
+    const double t = (double)(*step0 + step) * P.dtd;
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
+    const T* force = (forces && P.foff >= 0) ? forces + P.foff : nullptr;
+    fused_body<LAT, T, BX, BY>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
+                               local / ntile, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -242,9 +284,8 @@ static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
         if (e != hipSuccess) return hip_check(ctx, e, "fused kernel LDS attribute");
         attr_set = true;
     }
-    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
-    hipLaunchKernelGGL(kern, dim3(tiles0 * tiles1, chunks), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx), (const T*)fin,
-                       (const T*)force, (T*)fout, gt, gth, chunk, tiles0);
+    hipLaunchKernelGGL(kern, dim3(tiles0 * tiles1, chunks), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
+                       (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0);
     return hip_check(ctx, hipGetLastError(), "fused step launch");
 }
 
@@ -289,5 +330,43 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
 }
 
 void release_fast(dugks_ctx*) {}
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+static hipError_t batch_launch_t(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
+                                 long long nblocks, const void* fin, const void* forces, void* fout,
+                                 const long long* step0, int step, hipStream_t st)
+{
+    auto kern = k_fused_batch<LAT, T, BX, BY, MINW>;
+    const size_t lds = (size_t)3 * LAT::Q * BX * BY * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(BX * BY), lds, st, (const Inst<T>*)insts, bstart, geom, n,
+                       (const T*)fin, (const T*)forces, (T*)fout, step0, step);
+    return hipGetLastError();
+}
+
+// tile shape of the fused kernels: (columns along x, along y) incl. halo
+void fused_tile_shape(int lattice, int* bx, int* by)
+{
+    *bx = lattice == DUGKS_D3Q19 ? 18 : 128;
+    *by = lattice == DUGKS_D3Q19 ? 14 : 1;
+}
+
+hipError_t batch_step_launch(int lattice, int dtype, const void* insts, const long long* bstart, const BatchGeom* geom,
+                             int n, long long nblocks, const void* fin, const void* forces, void* fout,
+                             const long long* step0, int step, hipStream_t st)
+{
+    if (lattice == DUGKS_D2Q9)
+        return dtype == DUGKS_F64
+                   ? batch_launch_t<D2Q9, double, 128, 1, 2>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
+                   : batch_launch_t<D2Q9, float, 128, 1, 2>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
+    return dtype == DUGKS_F64
+               ? batch_launch_t<D3Q19, double, 18, 14, 1>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
+               : batch_launch_t<D3Q19, float, 18, 14, 2>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
+}
 
 }  // namespace dugks

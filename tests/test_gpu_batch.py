@@ -1,0 +1,126 @@
+"""Batched instances: one launch per step for many uneven problems must give,
+per instance, exactly the single-instance result; graph replays must equal
+eager runs; small instances are checked against the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import batch_instances, field
+
+torch = pytest.importorskip("torch")
+M = pytest.importorskip("paper_1411_6121_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def instance_cfg(spec, dtype, scale=1):
+    """cfg of one batch instance from a synthetic spec (cavity or periodic-x
+    channel, lid U = 0.1 or body force along +x); sizes divided by `scale`"""
+    nx, ny = max(spec["nx"] // scale, 4), max(spec["ny"] // scale, 4)
+    U, RT = spec["U"], 1.0 / 3.0
+    nu = U * ny / spec["Re"]
+    if spec["kind"] == "cavity":
+        bc = (1, 1, 1, 1, 0, 0)
+        uw = [[0, 0, 0], [0, 0, 0], [0, 0, 0], [U, 0, 0], [0, 0, 0], [0, 0, 0]]
+    else:
+        bc = (0, 0, 1, 1, 0, 0)
+        uw = [[0, 0, 0]] * 6
+    return dict(lattice=9, dtype=dtype, n=(nx, ny, 1), L=(float(nx), float(ny), 1.0), rho0=1.0, RT=RT,
+                tau=nu / RT, dt=0.5, bc=bc, uw=uw, G=(spec["force"], 0.0, 0.0))
+
+
+def make_set(dtype, count=10, scale=4):
+    specs = batch_instances(seed=3, count=count)
+    cfgs = [instance_cfg(s, dtype, scale) for s in specs]
+    # vary the time factor and give some instances a force field
+    for i, c in enumerate(cfgs):
+        c["omega"] = 0.01 * i
+        c["phase"] = 0.1 * i
+    forces = []
+    for i, c in enumerate(cfgs):
+        Q, D, shp = M.shape_of(c)
+        forces.append(None if i % 3 else torch.from_numpy(field(50 + i, (D,) + shp, 1e-5)).to(
+            "cuda", dtype=M.torch_dtype(c)))
+    return cfgs, forces
+
+
+def single_run(cfg, f0, nsteps, force):
+    fa = f0.clone()
+    fb = torch.empty_like(fa)
+    ctx = M.dugks_init(cfg, fb)
+    try:
+        which = M.dugks_run(ctx, fa, fb, nsteps, force, 0.0)
+        return (fb if which else fa).clone()
+    finally:
+        M.dugks_destroy(ctx)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_equals_single_instance_runs(dtype):
+    cfgs, forces = make_set(dtype)
+    say(f"[batch == single] {dtype} sizes={[c['n'][:2] for c in cfgs]}")
+    B = M.BatchSolver(cfgs, forces=forces)
+    try:
+        f0 = [B.state(i).clone() for i in range(len(cfgs))]
+        B.run(7)
+        B.run(6)  # the batch clock carries the time across runs
+        torch.cuda.synchronize()
+        for i, c in enumerate(cfgs):
+            ref = single_run(c, f0[i], 13, forces[i])
+            assert torch.equal(B.state(i), ref), f"instance {i} differs"
+    finally:
+        B.close()
+
+
+def test_graph_replays_equal_eager_runs():
+    cfgs, forces = make_set("f64", count=6)
+    say("[batch graph replay]")
+    Bg = M.BatchSolver(cfgs, forces=forces)
+    Be = M.BatchSolver(cfgs, forces=forces)
+    try:
+        for rep in range(3):
+            Bg.run(4, use_graph=True)
+            Be.run(4, use_graph=False)
+            torch.cuda.synchronize()
+            extra = Be.f.sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(extra)
+            for i in range(len(cfgs)):
+                assert torch.equal(Bg.state(i), Be.state(i)), f"replay {rep} instance {i}"
+    finally:
+        Bg.close()
+        Be.close()
+
+
+def test_batch_matches_oracle():
+    cfgs, forces = make_set("f64", count=4, scale=8)
+    say("[batch vs oracle]")
+    B = M.BatchSolver(cfgs, forces=forces)
+    try:
+        f0 = [B.state(i).cpu().numpy() for i in range(len(cfgs))]
+        B.run(10)
+        torch.cuda.synchronize()
+        for i, c in enumerate(cfgs):
+            oc = {k: v for k, v in c.items() if k != "dtype"}
+            fr = None if forces[i] is None else forces[i].cpu().numpy()
+            ref = O.run(oc, f0[i], 10, force=fr)
+            got = B.state(i).cpu().numpy()
+            assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12, i
+            # the initial state is the oracle's equilibrium at rest under the
+            # uniform acceleration (force fields enter from the first step)
+            assert np.abs(f0[i] - O.init(oc)).max() < 1e-14
+    finally:
+        B.close()
+
+
+def test_batch_rejects_mixed_lattices():
+    say("[batch invalid]")
+    a = instance_cfg(batch_instances(1, 1)[0], "f64", 8)
+    b = dict(a, lattice=19, n=(4, 4, 4), L=(4.0, 4.0, 4.0), bc=(1,) * 6)
+    with pytest.raises(M.DugksError) as ei:
+        M.BatchSolver([a, b])
+    assert ei.value.code == M.EINVAL
