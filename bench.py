@@ -177,7 +177,7 @@ def main():
         "data": "synthetic (cavity from rest, no external data)",
         "config": {"workload": workload, "cells": cells, "Q": Q, "global_batch": 1, "seq_len": args.n,
                    "parallelism": "single GPU", "dt": cfg["dt"], "tau": cfg["tau"],
-                   "kernel": "fused" if variant == 1 else "general"},
+                   "kernel": {0: "general", 1: "fused-twice", 2: "fused"}.get(variant, str(variant))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_step},

@@ -190,8 +190,10 @@ int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, doubl
 int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, const void* lam0,
                    void* grad_u, void* grad_force, void* stream);
 
-/* Which step kernel the context uses: 0 = general two-pass kernels,
- * 1 = fused single-launch kernel (diagnostics). */
+/* Which step kernel the context uses (diagnostics): 0 = general two-pass
+ * kernels, 1 = fused single launch with every interface evaluated by both
+ * neighbouring cells, 2 = fused single launch with every interface
+ * evaluated once (default). */
 int dugks_kernel_variant(const dugks_ctx* ctx);
 
 /*

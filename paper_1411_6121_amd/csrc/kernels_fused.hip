@@ -258,6 +258,231 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused_batch(const Inst<T>* __r
 }
 
 // ---------------------------------------------------------------------------
+// v2: every interface evaluated once.  Per plane: each column evaluates its
+// upper x (and y) interface (tile halo columns included) into an LDS face
+// buffer and each updating column its upper march-axis interface (kept in
+// registers for the next plane); after a barrier every updating cell takes
+// the differences of its two faces per axis (steps 8-9).
+// ---------------------------------------------------------------------------
+template <class LAT, typename T, int BX, int BY>
+__device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
+                                            T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
+                                            int ck, T* lds)
+{
+    constexpr int Q = LAT::Q, D = LAT::D, M = D - 1;
+    constexpr int NX = cross_count<LAT, 0>(), NY = cross_count<LAT, 1>();
+    constexpr int NM = cross_count<LAT, (D == 3 ? 2 : 1)>();
+    constexpr int SQ = BX * BY;
+    T* fxb = lds + 3 * Q * SQ;         // [NX][BY][BX] upper x faces
+    T* fyb = fxb + NX * SQ;            // [NY][BY][BX] upper y faces (3-D)
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int b0 = tile % tiles0, b1 = tile / tiles0;
+
+    int g[2], kind[2], src[2];
+    g[0] = b0 * (BX - 2) - 1 + tx;
+    g[1] = (D == 3) ? b1 * (BY - 2) - 1 + ty : 0;
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) {
+        const int N = P.n[a], x = g[a];
+        if (x >= 0 && x < N) { kind[a] = COL_CELL; src[a] = x; }
+        else if (P.per[a] && x == -1) { kind[a] = COL_CELL; src[a] = N - 1; }
+        else if (P.per[a] && x == N) { kind[a] = COL_CELL; src[a] = 0; }
+        else if (!P.per[a] && x == -1) { kind[a] = COL_GHOST_LO; src[a] = 0; }
+        else if (!P.per[a] && x == N) { kind[a] = COL_GHOST_HI; src[a] = N - 1; }
+        else { kind[a] = COL_OUT; src[a] = 0; }
+    }
+    if (D == 2) { kind[1] = COL_CELL; src[1] = 0; }
+    const bool cell_col = kind[0] == COL_CELL && kind[1] == COL_CELL;
+    const bool ghost_col = !cell_col && kind[0] != COL_OUT && kind[1] != COL_OUT;
+    const bool row_ok = (D == 2) || (g[1] >= 0 && g[1] < P.n[1] && ty >= 1 && ty <= BY - 2);
+    const bool col_ok = g[0] >= 0 && g[0] < P.n[0] && tx >= 1 && tx <= BX - 2;
+    const bool upd_col = cell_col && col_ok && row_ok;
+    // upper x face of this column: needed for faces 0..n0 of interior rows
+    const bool xface = (cell_col || ghost_col) && row_ok && tx <= BX - 2 && g[0] >= -1 && g[0] <= P.n[0] - 1;
+    // upper y face (3-D): faces 0..n1 of interior columns
+    const bool yface = (D == 3) && (cell_col || ghost_col) && col_ok && ty <= BY - 2 && g[1] >= -1 &&
+                       g[1] <= P.n[1] - 1;
+
+    const int nM = P.n[M];
+    const int p0 = ck * chunk;
+    const int p1 = min(p0 + chunk, nM);
+    const bool perM = P.per[M] != 0;
+    const CellMetric<T> cmx = upd_col_pre(P, 0, g[0]);
+    const CellMetric<T> cmy = D == 3 ? upd_col_pre(P, 1, g[1]) : cmx;
+
+    auto slot_ptr = [&](int p, int q) -> T* { return lds + ((long)(ring(p) * Q + q) * BY + ty) * BX + tx; };
+    auto lds_at = [&](int p, int q, int dx, int dy) -> T {
+        return lds[((long)(ring(p) * Q + q) * BY + (ty + dy)) * BX + (tx + dx)];
+    };
+    auto compute_plane = [&](int p) {
+        const int pp = perM ? ((p % nM) + nM) % nM : p;
+        if (cell_col) {
+            int c3[3];
+            c3[0] = src[0];
+            c3[1] = (D == 3) ? src[1] : pp;
+            c3[2] = (D == 3) ? pp : 0;
+            T v[Q];
+            phi_cell<LAT, T>(P, fin, force, int_idx(P, c3[0], c3[1], c3[2]), gt, v);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) slot_ptr(p, q)[0] = v[q];
+        }
+        __syncthreads();
+        if (ghost_col) {
+            int off[2][2];
+            T wt[2][2];
+            int cnt[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                cnt[a] = 1;
+                off[a][0] = 0; wt[a][0] = T(1);
+                off[a][1] = 0; wt[a][1] = T(0);
+                if (a < D - 1 && kind[a] == COL_GHOST_LO) {
+                    cnt[a] = 2;
+                    off[a][0] = 1; wt[a][0] = T(1) - P.rlo[a];
+                    off[a][1] = 2; wt[a][1] = P.rlo[a];
+                } else if (a < D - 1 && kind[a] == COL_GHOST_HI) {
+                    cnt[a] = 2;
+                    off[a][0] = -1; wt[a][0] = T(1) - P.rhi[a];
+                    off[a][1] = -2; wt[a][1] = P.rhi[a];
+                }
+            }
+            T acc[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] = T(0);
+            for (int i1 = 0; i1 < cnt[1]; ++i1)
+                for (int i0 = 0; i0 < cnt[0]; ++i0) {
+                    const T w = wt[0][i0] * wt[1][i1];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) acc[q] += w * lds_at(p, q, off[0][i0], off[1][i1]);
+                }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) slot_ptr(p, q)[0] = acc[q];
+        }
+        __syncthreads();
+    };
+    auto ghost_plane = [&](int p, int a, int b, T r) {
+        if (cell_col || ghost_col) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                slot_ptr(p, q)[0] = (T(1) - r) * slot_ptr(a, q)[0] + r * slot_ptr(b, q)[0];
+        }
+        __syncthreads();
+    };
+    auto phi_view = [&](int z) {
+        const int slot = Q * SQ;
+        return LdsPhi<LAT, T, BX, BY>{lds, ring(z) * slot + ty * BX + tx, (ring(z + 1) - ring(z)) * slot,
+                                      (ring(z - 1) - ring(z)) * slot};
+    };
+
+    int hi;
+    if (!perM && p0 == 0) {
+        compute_plane(0);
+        compute_plane(1);
+        ghost_plane(-1, 0, 1, P.rlo[M]);
+        hi = 1;
+    } else {
+        compute_plane(p0 - 1);
+        compute_plane(p0);
+        hi = p0;
+    }
+    // lower march-axis face of the first plane
+    T zlo[NM];
+    if (upd_col) {
+        int ci[3];
+        ci[0] = g[0];
+        ci[1] = (D == 3) ? g[1] : p0;
+        ci[2] = (D == 3) ? p0 : 0;
+        const CellMetric<T> cmm = load_metric(P, M, p0);
+        const auto ph = phi_view(p0);
+        if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, zlo);
+        else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, zlo);
+    }
+    for (int z = p0; z < p1; ++z) {
+        if (hi < z + 1) {
+            __syncthreads();  // ring slot of z+1 and the face buffers were read by the last update
+            if (!perM && z + 1 == nM) ghost_plane(z + 1, z, z - 1, P.rhi[M]);
+            else compute_plane(z + 1);
+            hi = z + 1;
+        } else {
+            __syncthreads();
+        }
+        int ci[3];
+        ci[0] = g[0];
+        ci[1] = (D == 3) ? g[1] : z;
+        ci[2] = (D == 3) ? z : 0;
+        const CellMetric<T> cmm = load_metric(P, M, z);
+        const auto ph = phi_view(z);
+        T zhi[NM];
+        if (xface) {
+            T v[NX];
+            if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, v);
+            else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, v);
+#pragma unroll
+            for (int k = 0; k < NX; ++k) fxb[(k * BY + ty) * BX + tx] = v[k];
+        }
+        if constexpr (D == 3) {
+            if (yface) {
+                T v[NY];
+                face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 1>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, v);
+#pragma unroll
+                for (int k = 0; k < NY; ++k) fyb[(k * BY + ty) * BX + tx] = v[k];
+            }
+        }
+        if (upd_col) {
+            if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, zhi);
+            else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, zhi);
+        }
+        __syncthreads();
+        if (upd_col) {
+            const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+            T acc[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T p = ph.get(q, ph.cur);
+                acc[q] = p + (p - fin[(long long)q * P.nc + cidx]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
+            }
+            const T sx = cmx.fdx * P.c, sm = cmm.fdx * P.c;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (LAT::e(q, 0) != 0) {
+                    const int k = cross_slot<LAT, 0>(q);
+                    const T d = fxb[(k * BY + ty) * BX + tx] - fxb[(k * BY + ty) * BX + tx - 1];
+                    acc[q] -= T(LAT::e(q, 0)) * sx * d;
+                }
+                if constexpr (D == 3) {
+                    if (LAT::e(q, 1) != 0) {
+                        const int k = cross_slot<LAT, 1>(q);
+                        const T d = fyb[(k * BY + ty) * BX + tx] - fyb[(k * BY + ty - 1) * BX + tx];
+                        acc[q] -= T(LAT::e(q, 1)) * (cmy.fdx * P.c) * d;
+                    }
+                }
+                if (LAT::e(q, M) != 0) {
+                    const int k = cross_slot<LAT, M>(q);
+                    acc[q] -= T(LAT::e(q, M)) * sm * (zhi[k] - zlo[k]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fout[(long long)q * P.nc + cidx] = acc[q];
+#pragma unroll
+            for (int k = 0; k < NM; ++k) zlo[k] = zhi[k];
+        }
+    }
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+__global__ __launch_bounds__(BX* BY, MINW) void k_fused2(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
+                                                          const T* __restrict__ force, T* __restrict__ fout,
+                                                          double t, int chunk, int tiles0)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Inst<T>& P = *Pp;
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
+    fused2_body<LAT, T, BX, BY>(P, fin, force, fout, gt, gth, chunk, tiles0, blockIdx.x, blockIdx.y,
+                                reinterpret_cast<T*>(smem_raw));
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // device copy of the instance parameters of the context (uploaded at init)
@@ -278,6 +503,28 @@ static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = (size_t)3 * LAT::Q * BX * BY * sizeof(T);
     auto kern = k_fused<LAT, T, BX, BY, MINW>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_check(ctx, e, "fused kernel LDS attribute");
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(tiles0 * tiles1, chunks), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
+                       (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0);
+    return hip_check(ctx, hipGetLastError(), "fused step launch");
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
+                         hipStream_t st, int chunk)
+{
+    constexpr int D = LAT::D, M = D - 1;
+    const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
+    const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
+    const int chunks = (P.n[M] + chunk - 1) / chunk;
+    const size_t lds = (size_t)(3 * LAT::Q + cross_count<LAT, 0>() + (D == 3 ? cross_count<LAT, 1>() : 0)) * BX * BY *
+                       sizeof(T);
+    auto kern = k_fused2<LAT, T, BX, BY, MINW>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -310,17 +557,27 @@ int setup_fast(dugks_ctx* ctx)
     ctx->fast = 0;
     const char* env = getenv("DUGKS_FORCE_GENERAL");
     if (env && env[0] == '1') return DUGKS_OK;
-    // the march axis needs two cells; in-plane axes are any size
-    ctx->fast = 1;
+    // 1: every face evaluated by both neighbours; 2: faces evaluated once
+    ctx->fast = 2;
+    const char* v = getenv("DUGKS_FUSED_VARIANT");
+    if (v && v[0] == '1') ctx->fast = 1;
     return DUGKS_OK;
 }
 
 int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, bool* handled)
 {
     *handled = false;
-    if (ctx->fast != 1) return DUGKS_OK;
+    if (ctx->fast != 1 && ctx->fast != 2) return DUGKS_OK;
     *handled = true;
     const int chunk = pick_chunk(ctx);
+    if (ctx->fast == 2) {
+        if (ctx->cfg.lattice == DUGKS_D3Q19) {
+            if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D3Q19, double, 18, 14, 1>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+            return launch_fused2<D3Q19, float, 18, 14, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+        }
+        if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D2Q9, double, 128, 1, 2>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+        return launch_fused2<D2Q9, float, 128, 1, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+    }
     if (ctx->cfg.lattice == DUGKS_D3Q19) {
         if (ctx->cfg.dtype == DUGKS_F64) return launch_fused<D3Q19, double, 18, 14, 1>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
         return launch_fused<D3Q19, float, 18, 14, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);

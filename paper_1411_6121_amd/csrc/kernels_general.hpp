@@ -495,6 +495,89 @@ __device__ __forceinline__ void axis_fluxes_ct(const Inst<T>& P, const ACC& ph, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// faces evaluated once (fused kernel v2): the value of the interface of axis
+// A with index f between the cells at offsets off and off+1 (relative to the
+// thread's cell), after steps 3-7; walls handled in place.
+// ---------------------------------------------------------------------------
+
+// index of velocity q among the velocities crossing a face of axis A
+template <class LAT, int A>
+__host__ __device__ constexpr int cross_slot(int q)
+{
+    int s = 0;
+    for (int r = 0; r < q; ++r)
+        if (LAT::e(r, A) != 0) ++s;
+    return s;
+}
+template <class LAT, int A>
+__host__ __device__ constexpr int cross_count()
+{
+    return cross_slot<LAT, A>(LAT::Q);
+}
+
+template <class LAT, typename T, class ACC, int A>
+__device__ __forceinline__ void recon_at(const Inst<T>& P, const ACC& ph, int off, T w, T gn, const CellMetric<T>& mx,
+                                         const CellMetric<T>& my, const CellMetric<T>& mz, T* out)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const auto bL = ph.base(A == 0 ? off : 0, A == 1 ? off : 0, A == 2 ? off : 0);
+    const auto bR = ph.base(A == 0 ? off + 1 : 0, A == 1 ? off + 1 : 0, A == 2 ? off + 1 : 0);
+    const T hcg = P.h * P.c * gn;
+    const T hc = P.h * P.c;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const T pL = ph.get(q, bL), pR = ph.get(q, bR);
+        T v = pL + w * (pR - pL) - T(LAT::e(q, A)) * hcg * (pR - pL);
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            if (t == A || LAT::e(q, t) == 0) continue;
+            const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
+            const auto u = ph.up(t), d = ph.dn(t);
+            const T dL = mt.cp * ph.get(q, bL + u) + mt.c0 * pL + mt.cm * ph.get(q, bL - d);
+            const T dR = mt.cp * ph.get(q, bR + u) + mt.c0 * pR + mt.cm * ph.get(q, bR - d);
+            v -= T(LAT::e(q, t)) * hc * (dL + w * (dR - dL));
+        }
+        out[q] = v;
+    }
+}
+
+// ci: global cell coordinates of the thread's cell (tangential ones are
+// used for metrics and force); f: face index along A.  out[cross_slot]
+// receives f_q (step 7) for the velocities crossing the face.
+template <class LAT, typename T, class ACC, int A>
+__device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
+                                          int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
+                                          const CellMetric<T>& mz, T* out)
+{
+    constexpr int Q = LAT::Q;
+    const AxisMetric<T>& m = P.m[A];
+    const int n = P.n[A];
+    const bool wall_lo = !P.per[A] && f == 0;
+    const bool wall_hi = !P.per[A] && f == n;
+    NeqInfo<LAT, T> info;
+    asm volatile("" ::: "memory");
+    T fb[Q], G[3];
+    if (wall_lo || wall_hi) {
+        // the opposite interface of the wall cell (its NEQ information)
+        const int fo = wall_lo ? 1 : n - 1;
+        const int oo = wall_lo ? off + 1 : off - 1;
+        recon_at<LAT, T, ACC, A>(P, ph, oo, m.w[fo], m.gn[fo], mx, my, mz, fb);
+        face_force<LAT, T>(P, force, A, fo, m.w[fo], ci, gth, G);
+        neq_capture<LAT, T>(P, A, fb, G, info);
+        asm volatile("" ::: "memory");
+    }
+    const T w = m.w[f];
+    recon_at<LAT, T, ACC, A>(P, ph, off, w, m.gn[f], mx, my, mz, fb);
+    face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
+    if (wall_lo) wall_rule<LAT, T>(P, 2 * A, fb, info);
+    if (wall_hi) wall_rule<LAT, T>(P, 2 * A + 1, fb, info);
+    face_original<LAT, T>(P, A, fb, G);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (LAT::e(q, A) != 0) out[cross_slot<LAT, A>(q)] = fb[q];
+}
+
 // Steps 3-9 for one cell: acc holds f~+ on entry (Eq. f_tilde_+) and the
 // updated state on exit.  Faces are taken one at a time; on a wall axis the
 // opposite (interior) face is evaluated first so that the NEQ rule can use

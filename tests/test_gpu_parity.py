@@ -34,19 +34,26 @@ def to_dev(a, cfg):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=tdt(cfg))
 
 
+VARIANTS = {"general": 0, "fused-twice": 1, "fused": 2}
+
+
 def make_ctx(cfg, fb, variant=None, **kw):
-    """context on the requested step kernel (None: library default = fused)"""
+    """context on the requested step kernel (None: library default = fused,
+    faces once); 'fused-twice' evaluates every face from both cells"""
     import os
-    old = os.environ.get("DUGKS_FORCE_GENERAL")
+    keys = ("DUGKS_FORCE_GENERAL", "DUGKS_FUSED_VARIANT")
+    old = {k: os.environ.get(k) for k in keys}
     os.environ["DUGKS_FORCE_GENERAL"] = "1" if variant == "general" else "0"
+    os.environ["DUGKS_FUSED_VARIANT"] = "1" if variant == "fused-twice" else "2"
     try:
         ctx = M.dugks_init(cfg, fb, **kw)
     finally:
-        if old is None:
-            del os.environ["DUGKS_FORCE_GENERAL"]
-        else:
-            os.environ["DUGKS_FORCE_GENERAL"] = old
-    assert M.dugks_kernel_variant(ctx) == (0 if variant == "general" else 1)
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+    assert M.dugks_kernel_variant(ctx) == VARIANTS[variant or "fused"]
     return ctx
 
 
@@ -118,7 +125,7 @@ def case_force(cfg, seed):
     return field(seed, (D,) + shp, 1e-4)
 
 
-@pytest.mark.parametrize("variant", ["fused", "general"])
+@pytest.mark.parametrize("variant", ["fused", "fused-twice", "general"])
 @pytest.mark.parametrize("cfg", CASES, ids=[c["name"] for c in CASES])
 def test_step_parity_f64(cfg, variant):
     say(f"[parity f64] {cfg['name']} n={cfg['n']} {variant}")
