@@ -22,6 +22,7 @@ struct dugks_ctx {
     dugks::Inst<double> pd;
     std::string err;
     int fast = 0;                 // fused-kernel variant selected at init (0 = none)
+    int chunk = 0;                // planes marched per workgroup (0 = automatic)
     void* adj = nullptr;          // adjoint scratch (device, lazily)
     size_t adj_bytes = 0;
 };

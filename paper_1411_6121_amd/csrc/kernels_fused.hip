@@ -225,36 +225,17 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restric
                                reinterpret_cast<T*>(smem_raw));
 }
 
-// Batched form: block b belongs to the instance i with bstart[i] <= b <
-// bstart[i+1]; the instance table holds each instance's state offset, force
-// offset, tile counts and chunk (BatchGeom).  Time of instance i at this
-// launch: t0 + step * dt_i.
-
-template <class LAT, typename T, int BX, int BY, int MINW>
-__global__ __launch_bounds__(BX* BY, MINW) void k_fused_batch(const Inst<T>* __restrict__ insts,
-                                                               const long long* __restrict__ bstart,
-                                                               const BatchGeom* __restrict__ geom, int ninst,
-                                                               const T* __restrict__ fin, const T* __restrict__ forces,
-                                                               T* __restrict__ fout,
-                                                               const long long* __restrict__ step0, int step)
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that each XCD receives one contiguous range of the
+// logical order (tiles fastest): tiles that share halo columns then run on
+// the same XCD at about the same time and read the shared lines from one L2.
+// A bijection on [0, nb) for any nb.
+__device__ __forceinline__ int xcd_order(int b, int nb)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const long long b = blockIdx.x;
-    int lo = 0, hi = ninst - 1;  // bstart[lo] <= b < bstart[hi+1]
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bstart[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const Inst<T>& P = insts[lo];
-    const BatchGeom g = geom[lo];
-    const int local = (int)(b - bstart[lo]);
-    const int ntile = g.tiles0 * g.tiles1;
-    const double t = (double)(*step0 + step) * P.dtd;
-    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
-    const T* force = (forces && P.foff >= 0) ? forces + P.foff : nullptr;
-    fused_body<LAT, T, BX, BY>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
-                               local / ntile, reinterpret_cast<T*>(smem_raw));
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, k = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
 // ---------------------------------------------------------------------------
@@ -264,7 +245,7 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused_batch(const Inst<T>* __r
 // registers for the next plane); after a barrier every updating cell takes
 // the differences of its two faces per axis (steps 8-9).
 // ---------------------------------------------------------------------------
-template <class LAT, typename T, int BX, int BY>
+template <class LAT, typename T, int BX, int BY, bool PF>
 __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                             T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                             int ck, T* lds)
@@ -304,6 +285,8 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
     const bool yface = (D == 3) && (cell_col || ghost_col) && col_ok && ty <= BY - 2 && g[1] >= -1 &&
                        g[1] <= P.n[1] - 1;
 
+    // workgroup-uniform: does the tile hold ghost columns (wall-side tiles)
+    const bool any_ghost = __syncthreads_or(ghost_col) != 0;
     const int nM = P.n[M];
     const int p0 = ck * chunk;
     const int p1 = min(p0 + chunk, nM);
@@ -315,19 +298,36 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
     auto lds_at = [&](int p, int q, int dx, int dy) -> T {
         return lds[((long)(ring(p) * Q + q) * BY + (ty + dy)) * BX + (tx + dx)];
     };
-    auto compute_plane = [&](int p) {
+    // state (and force field) of the plane a column computes next, loaded
+    // into registers one plane ahead of its use
+    T pf[Q], pg[3] = {T(0), T(0), T(0)};
+    auto plane_cell = [&](int p) -> long long {
         const int pp = perM ? ((p % nM) + nM) % nM : p;
+        return int_idx(P, src[0], (D == 3) ? src[1] : pp, (D == 3) ? pp : 0);
+    };
+    auto load_plane = [&](int p) {
+        if (PF && cell_col) {
+            const int pp = perM ? ((p % nM) + nM) % nM : p;
+            const long long ci = int_idx(P, src[0], (D == 3) ? src[1] : pp, (D == 3) ? pp : 0);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) pf[q] = fin[(long long)q * P.nc + ci];
+            if (force) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) pg[a] = force[(long long)a * P.nc + ci];
+            }
+        }
+    };
+    // f-bar-plus of plane p from the loaded registers
+    auto compute_plane = [&](int p) {
         if (cell_col) {
-            int c3[3];
-            c3[0] = src[0];
-            c3[1] = (D == 3) ? src[1] : pp;
-            c3[2] = (D == 3) ? pp : 0;
             T v[Q];
-            phi_cell<LAT, T>(P, fin, force, int_idx(P, c3[0], c3[1], c3[2]), gt, v);
+            if constexpr (PF) phi_from<LAT, T>(P, pf, pg, force != nullptr, gt, v);
+            else phi_cell<LAT, T>(P, fin, force, plane_cell(p), gt, v);
 #pragma unroll
             for (int q = 0; q < Q; ++q) slot_ptr(p, q)[0] = v[q];
         }
         __syncthreads();
+        if (!any_ghost) return;
         if (ghost_col) {
             int off[2][2];
             T wt[2][2];
@@ -375,17 +375,25 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
                                       (ring(z - 1) - ring(z)) * slot};
     };
 
+    // a plane computed (not extrapolated) by the march: 0 <= p < nM, or any
+    // p on a periodic march axis
+    auto computed = [&](int p) { return perM || p < nM; };
     int hi;
     if (!perM && p0 == 0) {
+        load_plane(0);
         compute_plane(0);
+        load_plane(1);
         compute_plane(1);
         ghost_plane(-1, 0, 1, P.rlo[M]);
         hi = 1;
     } else {
+        load_plane(p0 - 1);
         compute_plane(p0 - 1);
+        load_plane(p0);
         compute_plane(p0);
         hi = p0;
     }
+    if (PF && hi + 1 <= p1 && computed(hi + 1)) load_plane(hi + 1);
     // lower march-axis face of the first plane
     T zlo[NM];
     if (upd_col) {
@@ -401,9 +409,14 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
             __syncthreads();  // ring slot of z+1 and the face buffers were read by the last update
-            if (!perM && z + 1 == nM) ghost_plane(z + 1, z, z - 1, P.rhi[M]);
-            else compute_plane(z + 1);
+            if (!computed(z + 1)) {
+                ghost_plane(z + 1, z, z - 1, P.rhi[M]);
+            } else {
+                if (!PF) load_plane(z + 1);
+                compute_plane(z + 1);
+            }
             hi = z + 1;
+            if (PF && z + 2 <= p1 && computed(z + 2)) load_plane(z + 2);
         } else {
             __syncthreads();
         }
@@ -413,6 +426,15 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
         ci[2] = (D == 3) ? z : 0;
         const CellMetric<T> cmm = load_metric(P, M, z);
         const auto ph = phi_view(z);
+        // the cell's own state for Eq. (f_tilde_+), loaded before the faces
+        // (PF) or at the update
+        T fz[Q];
+        auto load_own = [&]() {
+            const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fz[q] = fin[(long long)q * P.nc + cidx];
+        };
+        if (PF && upd_col) load_own();
         T zhi[NM];
         if (xface) {
             T v[NX];
@@ -437,10 +459,11 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
         if (upd_col) {
             const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
             T acc[Q];
+            if (!PF) load_own();
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const T p = ph.get(q, ph.cur);
-                acc[q] = p + (p - fin[(long long)q * P.nc + cidx]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
+                acc[q] = p + (p - fz[q]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
             }
             const T sx = cmx.fdx * P.c, sm = cmm.fdx * P.c;
 #pragma unroll
@@ -470,16 +493,50 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
     }
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
 __global__ __launch_bounds__(BX* BY, MINW) void k_fused2(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
                                                           const T* __restrict__ force, T* __restrict__ fout,
-                                                          double t, int chunk, int tiles0)
+                                                          double t, int chunk, int tiles0, int tiles)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Inst<T>& P = *Pp;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
-    fused2_body<LAT, T, BX, BY>(P, fin, force, fout, gt, gth, chunk, tiles0, blockIdx.x, blockIdx.y,
+    const int ntile = (int)tiles;
+    const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    fused2_body<LAT, T, BX, BY, PF>(P, fin, force, fout, gt, gth, chunk, tiles0, b % ntile, b / ntile,
                                 reinterpret_cast<T*>(smem_raw));
+}
+
+// Batched form: workgroup b (in XCD order) belongs to the instance i with
+// bstart[i] <= b < bstart[i+1]; the instance table holds each instance's
+// state offset, force offset, tile counts and chunk (BatchGeom).  Time of
+// instance i at this launch: (step0 + step) * dt_i, with step0 a device
+// counter so that a captured graph replays with advancing time.
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
+__global__ __launch_bounds__(BX* BY, MINW) void k_fused2_batch(const Inst<T>* __restrict__ insts,
+                                                                const long long* __restrict__ bstart,
+                                                                const BatchGeom* __restrict__ geom, int ninst,
+                                                                const T* __restrict__ fin, const T* __restrict__ forces,
+                                                                T* __restrict__ fout,
+                                                                const long long* __restrict__ step0, int step)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const long long b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = ninst - 1;  // bstart[lo] <= b < bstart[hi+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bstart[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const Inst<T>& P = insts[lo];
+    const BatchGeom g = geom[lo];
+    const int local = (int)(b - bstart[lo]);
+    const int ntile = g.tiles0 * g.tiles1;
+    const double t = (double)(*step0 + step) * P.dtd;
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
+    const T* force = (forces && P.foff >= 0) ? forces + P.foff : nullptr;
+    fused2_body<LAT, T, BX, BY, PF>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
+                                    local / ntile, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -488,10 +545,23 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused2(const Inst<T>* __restri
 // device copy of the instance parameters of the context (uploaded at init)
 static const void* dev_inst(const dugks_ctx* ctx) { return ctx->inst_dev; }
 
-struct FusedShape {
-    int bx, by, chunk, tiles0, tiles1, chunks;
-    size_t lds;
-};
+// Plane prefetch (state of plane z+2 loaded during plane z) costs about
+// 2Q registers per thread: used where the kernel's occupancy target still
+// holds with them (D3Q19 FP64 runs one wave per SIMD anyway, D2Q9 FP32 has
+// room), not where it would spill (D3Q19 FP32, D2Q9 FP64 at two waves).
+template <class LAT, typename T>
+constexpr bool prefetch_planes()
+{
+    return (LAT::D == 3) == (sizeof(T) == 8);
+}
+
+// LDS of the v2 kernels: three f-bar-plus planes and the x (and y) face
+// buffers
+template <class LAT, typename T, int BX, int BY>
+static size_t fused2_lds()
+{
+    return (size_t)(3 * LAT::Q + cross_count<LAT, 0>() + (LAT::D == 3 ? cross_count<LAT, 1>() : 0)) * BX * BY * sizeof(T);
+}
 
 template <class LAT, typename T, int BX, int BY, int MINW>
 static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
@@ -514,7 +584,7 @@ static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     return hip_check(ctx, hipGetLastError(), "fused step launch");
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
 static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
                          hipStream_t st, int chunk)
 {
@@ -522,17 +592,18 @@ static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void
     const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
     const int chunks = (P.n[M] + chunk - 1) / chunk;
-    const size_t lds = (size_t)(3 * LAT::Q + cross_count<LAT, 0>() + (D == 3 ? cross_count<LAT, 1>() : 0)) * BX * BY *
-                       sizeof(T);
-    auto kern = k_fused2<LAT, T, BX, BY, MINW>;
+    const size_t lds = fused2_lds<LAT, T, BX, BY>();
+    auto kern = k_fused2<LAT, T, BX, BY, MINW, PF>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(ctx, e, "fused kernel LDS attribute");
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, dim3(tiles0 * tiles1, chunks), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
-                       (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0);
+    const long long nb = (long long)tiles0 * tiles1 * chunks;
+    if (nb > 0x7fffffffLL) return fail(ctx, DUGKS_EUNSUPPORTED, "mesh too large for one launch");
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
+                       (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0, tiles0 * tiles1);
     return hip_check(ctx, hipGetLastError(), "fused step launch");
 }
 
@@ -540,6 +611,7 @@ static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void
 // columns (126 interior); chunk = planes marched per workgroup
 static int pick_chunk(const dugks_ctx* ctx)
 {
+    if (ctx->chunk > 0) return std::min(ctx->chunk, std::max(ctx->cfg.n[ctx->D - 1], 1));
     const int D = ctx->D;
     const int nM = ctx->cfg.n[D - 1];
     long tiles;
@@ -561,6 +633,9 @@ int setup_fast(dugks_ctx* ctx)
     ctx->fast = 2;
     const char* v = getenv("DUGKS_FUSED_VARIANT");
     if (v && v[0] == '1') ctx->fast = 1;
+    // march length override (tuning sweeps)
+    const char* ch = getenv("DUGKS_CHUNK");
+    ctx->chunk = ch ? std::max(0, atoi(ch)) : 0;
     return DUGKS_OK;
 }
 
@@ -572,11 +647,11 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
     const int chunk = pick_chunk(ctx);
     if (ctx->fast == 2) {
         if (ctx->cfg.lattice == DUGKS_D3Q19) {
-            if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D3Q19, double, 18, 14, 1>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
-            return launch_fused2<D3Q19, float, 18, 14, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+            if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+            return launch_fused2<D3Q19, float, 18, 14, 2, prefetch_planes<D3Q19, float>()>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
         }
-        if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D2Q9, double, 128, 1, 2>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
-        return launch_fused2<D2Q9, float, 128, 1, 2>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+        if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D2Q9, double, 128, 1, 2, prefetch_planes<D2Q9, double>()>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+        return launch_fused2<D2Q9, float, 128, 1, 2, prefetch_planes<D2Q9, float>()>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
     }
     if (ctx->cfg.lattice == DUGKS_D3Q19) {
         if (ctx->cfg.dtype == DUGKS_F64) return launch_fused<D3Q19, double, 18, 14, 1>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
@@ -588,19 +663,20 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
 
 void release_fast(dugks_ctx*) {}
 
-template <class LAT, typename T, int BX, int BY, int MINW>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
 static hipError_t batch_launch_t(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
                                  long long nblocks, const void* fin, const void* forces, void* fout,
                                  const long long* step0, int step, hipStream_t st)
 {
-    auto kern = k_fused_batch<LAT, T, BX, BY, MINW>;
-    const size_t lds = (size_t)3 * LAT::Q * BX * BY * sizeof(T);
+    auto kern = k_fused2_batch<LAT, T, BX, BY, MINW, PF>;
+    const size_t lds = fused2_lds<LAT, T, BX, BY>();
     static bool attr = false;
     if (!attr) {
         const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr = true;
     }
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(BX * BY), lds, st, (const Inst<T>*)insts, bstart, geom, n,
                        (const T*)fin, (const T*)forces, (T*)fout, step0, step);
     return hipGetLastError();
@@ -619,11 +695,11 @@ hipError_t batch_step_launch(int lattice, int dtype, const void* insts, const lo
 {
     if (lattice == DUGKS_D2Q9)
         return dtype == DUGKS_F64
-                   ? batch_launch_t<D2Q9, double, 128, 1, 2>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
-                   : batch_launch_t<D2Q9, float, 128, 1, 2>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
+                   ? batch_launch_t<D2Q9, double, 128, 1, 2, prefetch_planes<D2Q9, double>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
+                   : batch_launch_t<D2Q9, float, 128, 1, 2, prefetch_planes<D2Q9, float>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
     return dtype == DUGKS_F64
-               ? batch_launch_t<D3Q19, double, 18, 14, 1>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
-               : batch_launch_t<D3Q19, float, 18, 14, 2>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
+               ? batch_launch_t<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
+               : batch_launch_t<D3Q19, float, 18, 14, 2, prefetch_planes<D3Q19, float>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
 }
 
 }  // namespace dugks

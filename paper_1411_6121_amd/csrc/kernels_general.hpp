@@ -31,18 +31,17 @@ __device__ __forceinline__ long long int_idx(const Inst<T>& P, int i, int j, int
     return ((long long)k * P.n[1] + j) * P.n[0] + i;
 }
 
-// f-bar-plus of one interior cell (Appendix step 1)
+// f-bar-plus of one interior cell (Appendix step 1) from its state fv[Q]
+// and its force-field values fg[D] (used if has_field)
 template <class LAT, typename T>
-__device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__ f, const T* __restrict__ force, long long ci,
-                         T gt, T* out)
+__device__ __forceinline__ void phi_from(const Inst<T>& P, const T (&fv)[LAT::Q], const T (&fg)[3], bool has_field,
+                                         T gt, T* out)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const T invRT = T(1) / P.RT;
-    T fv[Q];
     T rho = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        fv[q] = f[(long long)q * P.nc + ci];
         rho += fv[q];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -53,7 +52,7 @@ __device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__
     T G[3], u[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        G[a] = gt * (P.G0[a] + (force ? force[(long long)a * P.nc + ci] : T(0)));
+        G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
         u[a] = P.c * j[a] / P.rho0 + P.h * G[a];
     }
 #pragma unroll
@@ -62,6 +61,22 @@ __device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__
         const T S = src_fac<LAT, T>(q, u, G, P.c, invRT) * fe;
         out[q] = fv[q] + P.B1 * (fe - fv[q]) + P.C1 * S;
     }
+}
+
+// the same, loading the cell's state and force field from HBM
+template <class LAT, typename T>
+__device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__ f, const T* __restrict__ force, long long ci,
+                         T gt, T* out)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    T fv[Q], fg[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fv[q] = f[(long long)q * P.nc + ci];
+    if (force) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) fg[a] = force[(long long)a * P.nc + ci];
+    }
+    phi_from<LAT, T>(P, fv, fg, force != nullptr, gt, out);
 }
 
 template <class LAT, typename T>
