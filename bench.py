@@ -1,22 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the incompressible-DUGKS step on one MI355X.
 
-Workload (default): D3Q19 cubic lid-driven cavity, 128^3 cells, lid U = 0.1
+Workload (headline): D3Q19 cubic lid-driven cavity, 128^3 cells, lid U = 0.1
 along x, NEQ velocity walls on all six sides, rho0 = 1, RT = 1/3, dx = 1,
 Re = 100 (tau = U N / (Re RT)), CFL 0.5, FP64, started from rest.  One
 "step" is one full time step (Appendix steps 1-9) over every cell and every
-discrete velocity.  Prints one JSON line:
+discrete velocity: one launch of the fused step kernel.  Prints one JSON
+line:
 
   value      MLUPS = cells * steps / seconds / 1e6 (inputs resident in HBM)
-  roofline   dominant kernel's algorithmic HBM bytes (read f~ once, write f~
-             once: 2 Q s bytes per cell) / its average launch time, against
-             the 8 TB/s HBM peak; `traffic` = HBM bytes per launch measured
-             with rocprofv3 counters (profiles/), null when stale
+  roofline   the step kernel's algorithmic HBM bytes (read f~ once, write f~
+             once: 2 Q s bytes per cell) / its average launch time (HIP
+             events on the launch stream over the timed steps), against the
+             8 TB/s HBM peak; `traffic` = HBM bytes per launch measured with
+             rocprofv3 counters (profiles/traffic.json), null when the kernel
+             sources changed since
+  also       the same workload in FP32; 64 uneven D2Q9 instances advanced by
+             one batched launch per step (graph replay) vs 64 plain launches
+             per step; the adjoint step vs the forward step (D2Q9 256^2
+             periodic, FP64)
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample
              of the same workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
        [--mesh uniform|tanh] [--re 100] [--n 128] [--no-cpu-baseline]
+       [--no-extras]
+       python bench.py --summarize-counters FETCH_DIR WRITE_DIR
+         (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output of
+          `bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras
+          --copy-probe`: writes profiles/traffic.json)
 """
 import argparse
 import hashlib
@@ -74,7 +86,7 @@ def measured_traffic(workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, budget_s=20.0, max_steps=8):
+def cpu_baseline(cfg, budget_s=15.0, max_steps=1000):
     """The oracle as it stands, on the full workload, for a bounded number of
     steps (stops after the step that crosses budget_s)."""
     import numpy as np
@@ -96,6 +108,179 @@ def cpu_baseline(cfg, budget_s=20.0, max_steps=8):
                       f"({el:.1f} s wall, OpenMP over cells)"}
 
 
+def _events():
+    import torch
+
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_steps(ctx, cfg, cur, nxt, steps, warmup, force=None):
+    """ms per dugks_step (HIP events on the launch stream)"""
+    import torch
+
+    import paper_1411_6121_amd as M
+
+    for k in range(warmup):
+        M.dugks_step(ctx, cur, nxt, force, k * cfg["dt"])
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for k in range(steps):
+        M.dugks_step(ctx, cur, nxt, force, (warmup + k) * cfg["dt"])
+        cur, nxt = nxt, cur
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, cur
+
+
+def batch_cfg(spec, dtype):
+    """one instance of the uneven D2Q9 set: cavity (lid U) or periodic-x
+    channel driven by a uniform body force"""
+    nx, ny, U, RT = spec["nx"], spec["ny"], spec["U"], 1.0 / 3.0
+    nu = U * ny / spec["Re"]
+    if spec["kind"] == "cavity":
+        bc = (1, 1, 1, 1, 0, 0)
+        uw = [[0, 0, 0], [0, 0, 0], [0, 0, 0], [U, 0, 0], [0, 0, 0], [0, 0, 0]]
+    else:
+        bc = (0, 0, 1, 1, 0, 0)
+        uw = [[0, 0, 0]] * 6
+    return dict(lattice=9, dtype=dtype, n=(nx, ny, 1), L=(float(nx), float(ny), 1.0), rho0=1.0, RT=RT,
+                tau=nu / RT, dt=0.5, bc=bc, uw=uw, G=(spec["force"], 0.0, 0.0))
+
+
+def bench_batched(dtype="f64", count=64, steps=100, warmup=5):
+    """one batched launch per step (graph replay) vs one plain launch per
+    instance per step; both give bitwise-identical states"""
+    import torch
+
+    import paper_1411_6121_amd as M
+    from synthetic import batch_instances
+
+    cfgs = [batch_cfg(s, dtype) for s in batch_instances(seed=3, count=count)]
+    cells = sum(c["n"][0] * c["n"][1] for c in cfgs)
+    B = M.BatchSolver(cfgs)
+    try:
+        B.run(warmup, use_graph=True)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        B.run(steps, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+    finally:
+        B.close()
+    ctxs, bufs = [], []
+    try:
+        for c in cfgs:
+            Q, D, shp = M.shape_of(c)
+            f = torch.empty((Q,) + shp, dtype=M.torch_dtype(c), device="cuda")
+            bufs.append([f, torch.empty_like(f)])
+            ctxs.append(M.dugks_init(c, f))
+        for k in range(warmup):
+            for i, c in enumerate(cfgs):
+                M.dugks_step(ctxs[i], bufs[i][0], bufs[i][1], None, k * c["dt"])
+                bufs[i].reverse()
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        for k in range(steps):
+            for i, c in enumerate(cfgs):
+                M.dugks_step(ctxs[i], bufs[i][0], bufs[i][1], None, (warmup + k) * c["dt"])
+                bufs[i].reverse()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / steps
+    finally:
+        for x in ctxs:
+            M.dugks_destroy(x)
+    return {"workload": f"{count} D2Q9 instances, sides 64..512, Re 100..1000, {dtype}", "cells": cells,
+            "steps": steps, "ms_per_step_batched_graph": round(ms_b, 4), "ms_per_step_sequential": round(ms_s, 4),
+            "speedup": round(ms_s / ms_b, 3), "mlups_batched": round(cells / ms_b / 1e3, 1),
+            "accuracy": "bitwise identical to the plain launches"}
+
+
+def bench_adjoint(n=256, steps=50, warmup=5):
+    """adjoint step vs forward step, D2Q9 n^2 periodic, FP64, tau = 1, with a
+    body-force field (the gradient workload)"""
+    import torch
+
+    import paper_1411_6121_amd as M
+    from synthetic import gaussian_bumps
+
+    cfg = dict(lattice=9, dtype="f64", n=(n, n, 1), L=(float(n), float(n), 1.0), rho0=1.0, RT=1 / 3, tau=1.0,
+               dt=0.5, bc=(0,) * 6)
+    Q, D, shp = M.shape_of(cfg)
+    Gf = torch.from_numpy(gaussian_bumps(7, n)).to("cuda")
+    f = torch.empty((Q,) + shp, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(f)
+    ctx = M.dugks_init(cfg, f, force=Gf)
+    try:
+        ms_f, f = time_steps(ctx, cfg, f, g, steps, warmup, force=Gf)
+        lam = torch.ones_like(f)
+        lam2 = torch.empty_like(f)
+        gG = torch.zeros((D,) + shp, dtype=torch.float64, device="cuda")
+        for k in range(warmup):
+            M.dugks_step_adjoint(ctx, f, lam, lam2, Gf, 0.0, gG)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        for k in range(steps):
+            M.dugks_step_adjoint(ctx, f, lam, lam2, Gf, k * cfg["dt"], gG)
+            lam, lam2 = lam2, lam
+        e1.record()
+        torch.cuda.synchronize()
+        ms_a = e0.elapsed_time(e1) / steps
+    finally:
+        M.dugks_destroy(ctx)
+    return {"workload": f"D2Q9 {n}^2 periodic, force field, f64", "ms_forward_step": round(ms_f, 4),
+            "ms_adjoint_step": round(ms_a, 4), "ratio": round(ms_a / ms_f, 3)}
+
+
+def summarize_counters(fetch_dir, write_dir, workload):
+    """HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, each scaled by what the counter reads for the plain
+    256 MiB device copy in the same run; writes profiles/traffic.json"""
+    import csv
+    import statistics
+
+    def rows(d):
+        return list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+
+    def per_dispatch(rs, name):
+        step = [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == name and "k_fused2<" in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]
+                and int(r["Grid_Size"]) >= 65536]
+        return step, copy
+
+    probe_kib = 256 * 1024.0
+    fs, fc = per_dispatch(rows(fetch_dir), "FETCH_SIZE")
+    ws, wc = per_dispatch(rows(write_dir), "WRITE_SIZE")
+    if not (fs and fc and ws and wc):
+        raise SystemExit("counter files lack the step kernel or the 256 MiB copy probe")
+    kf = probe_kib / statistics.median(fc)
+    kw = probe_kib / statistics.median(wc)
+    fetch = statistics.mean(fs) * kf * 1024
+    write = statistics.mean(ws) * kw * 1024
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(p)) if os.path.exists(p) else {}
+    data[workload] = {"source_hash": source_hash(), "bytes_per_launch": round(fetch + write),
+                      "fetch_bytes": round(fetch), "write_bytes": round(write),
+                      "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
+                      "raw_fetch_kib": round(statistics.mean(fs), 1), "raw_write_kib": round(statistics.mean(ws), 1),
+                      "dispatches": len(fs)}
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    with open(p, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(data[workload]))
+
+
+def workload_name(n, mesh, re, dtype):
+    return f"D3Q19 {n}^3 lid-driven cavity, {mesh}, Re {re:g}, NEQ walls, {dtype}"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,9 +291,16 @@ def main():
     ap.add_argument("--re", type=float, default=100.0)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 / batched / adjoint figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+
+    workload = workload_name(args.n, args.mesh, args.re, args.dtype)
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, workload)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the step is measured on one MI355X); "
@@ -127,29 +319,14 @@ def main():
     f = torch.empty((Q,) + shp, dtype=M.torch_dtype(cfg), device="cuda")
     g = torch.empty_like(f)
     ctx = M.dugks_init(cfg, f)
-    cur, nxt = f, g
-    for k in range(args.warmup):
-        M.dugks_step(ctx, cur, nxt, None, k * cfg["dt"])
-        cur, nxt = nxt, cur
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
-    ev0.record(stream)
-    for k in range(args.steps):
-        M.dugks_step(ctx, cur, nxt, None, (args.warmup + k) * cfg["dt"])
-        cur, nxt = nxt, cur
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms, cur = time_steps(ctx, cfg, f, g, args.steps, args.warmup)
     wall = time.perf_counter() - t_wall
-    ms = ev0.elapsed_time(ev1) / args.steps
-
     # state must stay finite (the step ran for real)
     tot = M.dugks_moments(ctx, cur)
     variant = M.dugks_kernel_variant(ctx)
     M.dugks_destroy(ctx)
+    del f, g, cur
 
     if args.copy_probe:
         buf = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 256 MiB
@@ -157,8 +334,8 @@ def main():
         for _ in range(3):
             out.copy_(buf)
         torch.cuda.synchronize()
+        del buf, out
 
-    workload = f"D3Q19 {args.n}^3 lid-driven cavity, {args.mesh}, Re {args.re:g}, NEQ walls, {args.dtype}"
     bytes_per_step = 2.0 * Q * esize * cells
     achieved = bytes_per_step / (ms * 1e-3) / 1e9
     traffic = measured_traffic(workload)
@@ -184,6 +361,22 @@ def main():
         "wall_s_timed": round(wall, 3),
         "mass_total": tot[0],
     }
+    if not args.no_extras:
+        also = {}
+        if args.dtype == "f64":
+            c32 = cavity_cfg(args.n, "f32", args.mesh, args.re)
+            f = torch.empty((Q,) + shp, dtype=torch.float32, device="cuda")
+            g = torch.empty_like(f)
+            ctx = M.dugks_init(c32, f)
+            ms32, _ = time_steps(ctx, c32, f, g, args.steps, args.warmup)
+            M.dugks_destroy(ctx)
+            del f, g
+            b32 = 2.0 * Q * 4 * cells
+            also["f32"] = {"ms_per_step": round(ms32, 5), "mlups": round(cells / ms32 / 1e3, 2),
+                           "hbm_frac": round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        also["batched"] = bench_batched()
+        also["adjoint"] = bench_adjoint()
+        res["also"] = also
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)
