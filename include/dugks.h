@@ -114,8 +114,8 @@ const char* dugks_last_error(const dugks_ctx* ctx);
 double dugks_dt_from_cfl(const dugks_config* cfg, double cfl);
 
 /*
- * Create a context and write the initial state (Sec. III: "initialised by
- * the equilibrium"): f~0 = feq(rho, u) - dt/2 S(rho, u, G(x, t0)) with the
+ * Create a context and write the initial state (the runs of Sec. III start
+ * from equilibrium): f~0 = feq(rho, u) - dt/2 S(rho, u, G(x, t0)) with the
  * incompressible equilibrium of Eq. (icfeq) and S of Eq. (S), i.e. the
  * state whose original distribution is the equilibrium.
  *   rho    nullable scalar field (NULL: rho0 everywhere)

@@ -12,8 +12,9 @@
  * Every loop over points writes disjoint outputs in a fixed per-point
  * operation order, so results do not depend on the thread count.
  *
- * Parity status of each function is recorded in the oracle section of
- * the design doc and pinned by tests/test_oracle_*.py.
+ * Every public function is pinned by tests/test_oracle_*.py to what the
+ * paper and the mathematics fix (printed tables, closed forms, invariants,
+ * analytic flows, finite differences), never to the HIP path.
  */
 #include "dugks_oracle.h"
 

@@ -10,7 +10,8 @@
  * The step follows the Appendix algorithm (steps 1-10) literally, over the
  * explicit point sets X_c (cell centres), X_cg (ghost centres), X_b (face
  * mid-points) and X_bc (interface cross points: 2-D corners, 3-D edge
- * mid-points), with the readings of the paper listed in the design doc.
+ * mid-points).  Where the paper is silent or garbled, the reading taken is
+ * stated at the code that applies it.
  *
  * Array layout at the interface (same as the product's, documented there):
  *   distributions  f[q][z][y][x]  (x fastest), q in the lattice order below

@@ -1,0 +1,104 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times: the D3Q19 128^3 cavity (uniform and tanh meshes, FP64 and
+FP32), the D2Q9 1024^2 cavity, and the 64-instance uneven batch.
+
+Whole-field comparisons: one oracle step at these sizes takes well under a
+second on the host cores, so every output value is checked, not a sample.
+"""
+import numpy as np
+import pytest
+
+import bench
+import oracle as O
+from synthetic import batch_instances, field, perturb
+
+torch = pytest.importorskip("torch")
+M = pytest.importorskip("paper_1411_6121_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_linf(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def flow_state(cfg, seed):
+    """the oracle's equilibrium of a seeded density/velocity field, perturbed
+    off equilibrium (a state with every term of the step active)"""
+    Q, D, shp = M.shape_of(cfg)
+    f0 = O.init(cfg, rho=1.0 + field(seed, shp, 0.01), u=field(seed + 1, (D,) + shp, 0.03))
+    return perturb(seed + 2, f0, 1e-3)
+
+
+def gpu_steps(cfg, f0, nsteps):
+    dt = torch.float64 if cfg["dtype"] == "f64" else torch.float32
+    fa = torch.from_numpy(f0).to(device="cuda", dtype=dt)
+    fb = torch.empty_like(fa)
+    ctx = M.dugks_init(cfg, fb)
+    try:
+        assert M.dugks_kernel_variant(ctx) == 2  # the benchmarked fused kernel
+        which = M.dugks_run(ctx, fa, fb, nsteps, None, 0.0)
+        torch.cuda.synchronize()
+        return (fb if which else fa).double().cpu().numpy()
+    finally:
+        M.dugks_destroy(ctx)
+
+
+@pytest.mark.parametrize("mesh,re", [("uniform", 100.0), ("tanh", 1000.0)])
+def test_cavity_128_f64(mesh, re):
+    cfg = bench.cavity_cfg(128, "f64", mesh, re)
+    say(f"[full size] D3Q19 128^3 cavity {mesh} Re {re:g} f64")
+    oc = {k: v for k, v in cfg.items() if k != "dtype"}
+    f0 = flow_state(oc, 61)
+    ref = O.run(oc, f0, 2)
+    got = gpu_steps(cfg, f0, 2)
+    assert rel_linf(got, ref) < 1e-12
+
+
+def test_cavity_128_f32_velocity():
+    cfg = bench.cavity_cfg(128, "f32", "uniform", 100.0)
+    say("[full size] D3Q19 128^3 cavity f32")
+    oc = {k: v for k, v in cfg.items() if k != "dtype"}
+    f0 = flow_state(oc, 62)
+    ref = O.run(oc, f0, 2)
+    got = gpu_steps(cfg, f0, 2)
+    _, u_ref, _, _ = O.moments(oc, ref)
+    _, u_got, _, _ = O.moments(oc, got)
+    assert np.abs(u_got - u_ref).max() / 0.1 < 2e-5
+
+
+def test_cavity_1024_d2q9_f64():
+    cfg = bench.cavity_cfg(1024, "f64", "uniform", 1000.0, lattice=9)
+    say("[full size] D2Q9 1024^2 cavity Re 1000 f64")
+    oc = {k: v for k, v in cfg.items() if k != "dtype"}
+    f0 = flow_state(oc, 63)
+    ref = O.run(oc, f0, 2)
+    got = gpu_steps(cfg, f0, 2)
+    assert rel_linf(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_batch_equals_plain_launches(dtype):
+    cfgs = [bench.batch_cfg(s, dtype) for s in batch_instances(seed=3, count=64)]
+    say(f"[full size] 64-instance batch {dtype}, {sum(c['n'][0] * c['n'][1] for c in cfgs)} cells")
+    B = M.BatchSolver(cfgs)
+    try:
+        f0 = [B.state(i).clone() for i in range(len(cfgs))]
+        B.run(3, use_graph=True)
+        torch.cuda.synchronize()
+        for i, c in enumerate(cfgs):
+            fa = f0[i].clone()
+            fb = torch.empty_like(fa)
+            ctx = M.dugks_init(c, fb)
+            try:
+                which = M.dugks_run(ctx, fa, fb, 3, None, 0.0)
+                ref = fb if which else fa
+                assert torch.equal(B.state(i), ref), f"instance {i}"
+            finally:
+                M.dugks_destroy(ctx)
+    finally:
+        B.close()
