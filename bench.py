@@ -161,6 +161,7 @@ def bench_batched(dtype="f64", count=64, steps=100, warmup=5):
     cells = sum(c["n"][0] * c["n"][1] for c in cfgs)
     B = M.BatchSolver(cfgs)
     try:
+        tile, chunk = B.tune(nsteps=3)
         B.run(warmup, use_graph=True)
         torch.cuda.synchronize()
         e0, e1 = _events()
@@ -198,6 +199,7 @@ def bench_batched(dtype="f64", count=64, steps=100, warmup=5):
     return {"workload": f"{count} D2Q9 instances, sides 64..512, Re 100..1000, {dtype}", "cells": cells,
             "steps": steps, "ms_per_step_batched_graph": round(ms_b, 4), "ms_per_step_sequential": round(ms_s, 4),
             "speedup": round(ms_s / ms_b, 3), "mlups_batched": round(cells / ms_b / 1e3, 1),
+            "tuned": {"tile_variant": tile, "chunk": chunk},
             "accuracy": "bitwise identical to the plain launches"}
 
 

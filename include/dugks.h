@@ -245,6 +245,24 @@ int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
                     const int64_t* force_offsets, int nsteps, int use_graph, void* stream,
                     int* which_out);
 
+/*
+ * Autotuner of the batched launch: times nsteps steps (after one warm-up
+ * step) for every tile shape of the lattice (D3Q19: 18 x 14 columns; D2Q9:
+ * rows of 128, 64 or 256 columns) and march chunk 4, 8, 16, 32, 64 planes,
+ * and keeps the fastest for later dugks_batch_run calls.  Results do not
+ * depend on the choice (every interface is evaluated by the same code in
+ * any tiling), so tuning never changes a state.
+ *   f_a, f_b   two distinct caller-owned scratch buffers of the batch's
+ *              size, holding a valid state (e.g. copies of the current
+ *              one); both are overwritten
+ *   forces, force_offsets  as in dugks_batch_run (the tuned workload)
+ *   tile_out, chunk_out    nullable: the chosen tile variant and chunk
+ * Synchronises the stream; the batch clock is left unchanged.  Drops any
+ * captured graph.  DUGKS_EINVAL for bad arguments or nsteps < 1.
+ */
+int dugks_batch_tune(dugks_batch* b, void* f_a, void* f_b, const void* forces, const int64_t* force_offsets,
+                     int nsteps, void* stream, int* tile_out, int* chunk_out);
+
 void dugks_batch_destroy(dugks_batch* b);
 
 /* Message of the last failure on b (NULL: the last failed

@@ -97,6 +97,9 @@ def load():
                                     ctypes.POINTER(I)]
     lib.dugks_batch_destroy.argtypes = [_VP]
     lib.dugks_batch_destroy.restype = None
+    lib.dugks_batch_tune.restype = I
+    lib.dugks_batch_tune.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), I, _VP,
+                                     ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.dugks_batch_last_error.restype = ctypes.c_char_p
     lib.dugks_batch_last_error.argtypes = [_VP]
     _lib = lib
@@ -377,6 +380,20 @@ class BatchSolver:
             self.f, self.g = self.g, self.f
         self.steps += int(nsteps)
         return self.f
+
+    def tune(self, nsteps=3):
+        """Pick the fastest tile shape and march chunk for this batch
+        (dugks_batch_tune) on scratch copies of the current state; the state
+        and the batch clock are unchanged.  Returns (tile_variant, chunk)."""
+        import torch
+
+        a = self.f.clone()
+        b = torch.empty_like(a)
+        tile, chunk = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(load().dugks_batch_tune(_VP(self.h), _ptr(a), _ptr(b), _ptr(self.forces), self.force_offsets,
+                                            int(nsteps), _stream(None), ctypes.byref(tile), ctypes.byref(chunk)))
+        del a, b
+        return tile.value, chunk.value
 
     def close(self):
         if self.h:

@@ -4,6 +4,7 @@
 // launches of a run can be captured once into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -12,17 +13,18 @@
 #include "kernels_general.hpp"
 
 namespace dugks {
-hipError_t batch_step_launch(int lattice, int dtype, const void* insts, const long long* bstart, const BatchGeom* geom,
-                             int n, long long nblocks, const void* fin, const void* forces, void* fout,
-                             const long long* step0, int step, hipStream_t st);
+hipError_t batch_step_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
+                             const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
+                             void* fout, const long long* step0, int step, hipStream_t st);
+int fused_tile_variants(int lattice);
+void fused_tile_shape(int lattice, int variant, int* bx, int* by);
 
-// batch clock: set / advance the device-side step counter (kernel nodes, so
-// a captured run replays them)
+// batch clock: set (reset != 0: s = add) or advance (s += add) the
+// device-side step counter (kernel nodes, so a captured run replays them)
 __global__ void k_batch_clock(long long* s, long long add, int reset)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *s = reset ? 0 : *s + add;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *s = reset ? add : *s + add;
 }
-void fused_tile_shape(int lattice, int* bx, int* by);
 
 // initial state of every instance: rest at rho0 (Sec. III), t = t0
 template <class LAT, typename T>
@@ -47,7 +49,7 @@ using namespace dugks;
 
 struct dugks_batch {
     int n = 0, lattice = 0, dtype = 0, D = 0, Q = 0, esize = 0;
-    int bx = 0, by = 0;
+    int tile = 0, chunk = 0;  // tile-shape variant and march chunk (0 = default) in use
     std::vector<dugks_config> cfgs;
     std::vector<unsigned char> hinst;  // host images of Inst<T>, n of them
     void* insts_dev = nullptr;
@@ -57,7 +59,6 @@ struct dugks_batch {
     long long* step_dev = nullptr;  // device step counter (batch clock)
     BatchGeom* geom_dev = nullptr;
     long long nblocks = 0, ncells = 0;
-    size_t lds = 0;
     std::string err = "no error";
     // captured run
     hipGraphExec_t gexec = nullptr;
@@ -77,11 +78,50 @@ static int bfail(dugks_batch* b, int code, const std::string& m)
     return code;
 }
 
+static void drop_graph(dugks_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->g_steps = -1;
+}
+
 namespace dugks {
 template <typename T>
 void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& met_host);
 size_t metric_len(const dugks_config* c);
 }  // namespace dugks
+
+// Workgroup geometry of every instance for tile-shape variant `tile` and
+// march chunk `chunk` (0: 16 planes in 3-D, 8 in 2-D): tile counts, chunk and
+// the workgroup prefix sum; uploaded synchronously (never inside a capture).
+static int set_geometry(dugks_batch* b, int tile, int chunk)
+{
+    const int n = b->n, D = b->D, M = D - 1;
+    int bx, by;
+    fused_tile_shape(b->lattice, tile, &bx, &by);
+    std::vector<long long> bstart(n + 1, 0);
+    std::vector<BatchGeom> geom(n);
+    for (int i = 0; i < n; ++i) {
+        const int* nn = b->cfgs[i].n;
+        BatchGeom g;
+        g.tiles0 = (nn[0] + bx - 3) / (bx - 2);
+        g.tiles1 = D == 3 ? (nn[1] + by - 3) / (by - 2) : 1;
+        g.chunk = std::min(chunk > 0 ? chunk : (D == 3 ? 16 : 8), nn[M]);
+        g.pad = 0;
+        const int chunks = (nn[M] + g.chunk - 1) / g.chunk;
+        geom[i] = g;
+        bstart[i + 1] = bstart[i] + (long long)g.tiles0 * g.tiles1 * chunks;
+    }
+    if (bstart[n] > 0x7fffffffLL) return bfail(b, DUGKS_EUNSUPPORTED, "batch too large for one launch");
+    if (hipMemcpy(b->bstart_dev, bstart.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->geom_dev, geom.data(), sizeof(BatchGeom) * n, hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, DUGKS_EHIP, "batch geometry upload");
+    drop_graph(b);
+    b->nblocks = bstart[n];
+    b->tile = tile;
+    b->chunk = chunk;
+    return DUGKS_OK;
+}
 
 template <typename T>
 static int build_tables(dugks_batch* b, const int64_t* offsets, hipStream_t st)
@@ -93,8 +133,7 @@ static int build_tables(dugks_batch* b, const int64_t* offsets, hipStream_t st)
     std::vector<T> mall;
     mall.reserve(mtot);
     std::vector<Inst<T>> insts(n);
-    std::vector<long long> bstart(n + 1, 0), cstart(n + 1, 0);
-    std::vector<BatchGeom> geom(n);
+    std::vector<long long> cstart(n + 1, 0);
     size_t moff = 0;
     for (int i = 0; i < n; ++i) {
         std::vector<T> mh;
@@ -103,18 +142,8 @@ static int build_tables(dugks_batch* b, const int64_t* offsets, hipStream_t st)
         mall.insert(mall.end(), mh.begin(), mh.end());
         insts[i].off = offsets[i];
         insts[i].foff = -1;
-        const int D = b->D, M = D - 1;
-        BatchGeom g;
-        g.tiles0 = (insts[i].n[0] + b->bx - 3) / (b->bx - 2);
-        g.tiles1 = D == 3 ? (insts[i].n[1] + b->by - 3) / (b->by - 2) : 1;
-        g.chunk = D == 3 ? 16 : 8;
-        g.pad = 0;
-        const int chunks = (insts[i].n[M] + g.chunk - 1) / g.chunk;
-        geom[i] = g;
-        bstart[i + 1] = bstart[i] + (long long)g.tiles0 * g.tiles1 * chunks;
         cstart[i + 1] = cstart[i] + insts[i].nc;
     }
-    b->nblocks = bstart[n];
     b->ncells = cstart[n];
     b->hinst.resize(sizeof(Inst<T>) * n);
     std::memcpy(b->hinst.data(), insts.data(), b->hinst.size());
@@ -126,12 +155,10 @@ static int build_tables(dugks_batch* b, const int64_t* offsets, hipStream_t st)
         return bfail(b, DUGKS_ENOMEM, "batch table allocation");
     if (hipMemcpy(b->met_dev, mall.data(), mall.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->insts_dev, b->hinst.data(), b->hinst.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->bstart_dev, bstart.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->cstart_dev, cstart.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->geom_dev, geom.data(), sizeof(BatchGeom) * n, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(b->cstart_dev, cstart.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess)
         return bfail(b, DUGKS_EHIP, "batch table upload");
     (void)st;
-    return DUGKS_OK;
+    return set_geometry(b, 0, 0);
 }
 
 extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t* offsets, void* stream,
@@ -154,8 +181,6 @@ extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t
     b->D = b->lattice == DUGKS_D2Q9 ? 2 : 3;
     b->Q = b->lattice;
     b->esize = b->dtype == DUGKS_F64 ? 8 : 4;
-    fused_tile_shape(b->lattice, &b->bx, &b->by);
-    b->lds = (size_t)3 * b->Q * b->bx * b->by * b->esize;
     b->cfgs.assign(cfgs, cfgs + n);
     const int rc = b->dtype == DUGKS_F64 ? build_tables<double>(b, offsets, (hipStream_t)stream)
                                          : build_tables<float>(b, offsets, (hipStream_t)stream);
@@ -190,16 +215,9 @@ extern "C" int dugks_batch_init(dugks_batch* b, void* f_out, void* stream)
 
 static int batch_launch_any(dugks_batch* b, const void* fin, void* fout, const void* forces, int step, hipStream_t st)
 {
-    const hipError_t e = batch_step_launch(b->lattice, b->dtype, b->insts_dev, b->bstart_dev, b->geom_dev, b->n,
+    const hipError_t e = batch_step_launch(b->lattice, b->dtype, b->tile, b->insts_dev, b->bstart_dev, b->geom_dev, b->n,
                                            b->nblocks, fin, forces, fout, b->step_dev, step, st);
     return e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EHIP, hipGetErrorString(e));
-}
-
-static void drop_graph(dugks_batch* b)
-{
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-    b->g_steps = -1;
 }
 
 static int launch_run(dugks_batch* b, const void* f_in, void* f_out, const void* forces, int nsteps, hipStream_t st)
@@ -218,14 +236,9 @@ static int launch_run(dugks_batch* b, const void* f_in, void* f_out, const void*
     return e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EHIP, hipGetErrorString(e));
 }
 
-extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
-                               const int64_t* force_offsets, int nsteps, int use_graph, void* stream, int* which_out)
+// per-instance force offsets into the instance table (before any launch)
+static int apply_force_offsets(dugks_batch* b, const void* forces, const int64_t* force_offsets)
 {
-    if (!b) return bfail(nullptr, DUGKS_EINVAL, "null batch");
-    if (!f_in || !f_out || f_in == f_out) return bfail(b, DUGKS_EINVAL, "need two distinct state buffers");
-    if (nsteps < 0) return bfail(b, DUGKS_EINVAL, "negative step count");
-    const hipStream_t st = (hipStream_t)stream;
-    // per-instance force offsets (instance table update, before any launch)
     bool changed = false;
     const size_t isz = b->dtype == DUGKS_F64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
     for (int i = 0; i < b->n; ++i) {
@@ -239,6 +252,18 @@ extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const vo
         if (hipMemcpy(b->insts_dev, b->hinst.data(), b->hinst.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bfail(b, DUGKS_EHIP, "instance table update");
     }
+    return DUGKS_OK;
+}
+
+extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
+                               const int64_t* force_offsets, int nsteps, int use_graph, void* stream, int* which_out)
+{
+    if (!b) return bfail(nullptr, DUGKS_EINVAL, "null batch");
+    if (!f_in || !f_out || f_in == f_out) return bfail(b, DUGKS_EINVAL, "need two distinct state buffers");
+    if (nsteps < 0) return bfail(b, DUGKS_EINVAL, "negative step count");
+    const hipStream_t st = (hipStream_t)stream;
+    const int frc = apply_force_offsets(b, forces, force_offsets);
+    if (frc != DUGKS_OK) return frc;
     if (use_graph) {
         if (!st) return bfail(b, DUGKS_EINVAL, "graph capture needs a non-default stream");
         if (!b->gexec || b->g_in != f_in || b->g_out != f_out || b->g_forces != forces || b->g_steps != nsteps ||
@@ -263,6 +288,59 @@ extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const vo
         if (rc != DUGKS_OK) return rc;
     }
     if (which_out) *which_out = nsteps & 1;
+    return DUGKS_OK;
+}
+
+extern "C" int dugks_batch_tune(dugks_batch* b, void* f_a, void* f_b, const void* forces,
+                                const int64_t* force_offsets, int nsteps, void* stream, int* tile_out,
+                                int* chunk_out)
+{
+    if (!b) return bfail(nullptr, DUGKS_EINVAL, "null batch");
+    if (!f_a || !f_b || f_a == f_b) return bfail(b, DUGKS_EINVAL, "need two distinct scratch buffers");
+    if (nsteps < 1) return bfail(b, DUGKS_EINVAL, "need at least one timed step per candidate");
+    const hipStream_t st = (hipStream_t)stream;
+    const int frc = apply_force_offsets(b, forces, force_offsets);
+    if (frc != DUGKS_OK) return frc;
+    // the clock is restored afterwards: tuning steps do not advance the batch
+    long long clock = 0;
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(&clock, b->step_dev, sizeof(long long), hipMemcpyDeviceToHost) != hipSuccess)
+        return bfail(b, DUGKS_EHIP, "clock read");
+    int maxm = 1;
+    for (const auto& c : b->cfgs) maxm = std::max(maxm, c.n[b->D - 1]);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return bfail(b, DUGKS_EHIP, "event create");
+    }
+    float best = -1.0f;
+    int best_tile = 0, best_chunk = 0, rc = DUGKS_OK;
+    static const int chunks[] = {4, 8, 16, 32, 64};
+    for (int tile = 0; tile < fused_tile_variants(b->lattice) && rc == DUGKS_OK; ++tile) {
+        for (int chunk : chunks) {
+            if (chunk > 2 * maxm) continue;
+            rc = set_geometry(b, tile, chunk);
+            if (rc == DUGKS_OK) rc = launch_run(b, f_a, f_b, forces, 1, st);  // warm-up
+            if (rc == DUGKS_OK && hipEventRecord(e0, st) != hipSuccess) rc = bfail(b, DUGKS_EHIP, "event record");
+            if (rc == DUGKS_OK) rc = launch_run(b, f_a, f_b, forces, nsteps, st);
+            if (rc == DUGKS_OK && hipEventRecord(e1, st) != hipSuccess) rc = bfail(b, DUGKS_EHIP, "event record");
+            float ms = 0.0f;
+            if (rc == DUGKS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = bfail(b, DUGKS_EHIP, "event timing");
+            if (rc != DUGKS_OK) break;
+            if (best < 0.0f || ms < best) { best = ms; best_tile = tile; best_chunk = chunk; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DUGKS_OK) return rc;
+    rc = set_geometry(b, best_tile, best_chunk);
+    if (rc != DUGKS_OK) return rc;
+    hipLaunchKernelGGL(k_batch_clock, dim3(1), dim3(1), 0, st, b->step_dev, clock, 1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, DUGKS_EHIP, hipGetErrorString(e));
+    if (tile_out) *tile_out = best_tile;
+    if (chunk_out) *chunk_out = best_chunk;
     return DUGKS_OK;
 }
 

@@ -682,24 +682,41 @@ static hipError_t batch_launch_t(const void* insts, const long long* bstart, con
     return hipGetLastError();
 }
 
-// tile shape of the fused kernels: (columns along x, along y) incl. halo
-void fused_tile_shape(int lattice, int* bx, int* by)
+// Tile shapes of the batched kernel: (columns along x, along y) incl. halo.
+// D3Q19 has one (18 x 14: the FP64 LDS ring fills a CU); D2Q9 rows of 128
+// (default), 64 or 256 columns, chosen per batch by the autotuner.
+int fused_tile_variants(int lattice) { return lattice == DUGKS_D3Q19 ? 1 : 3; }
+
+void fused_tile_shape(int lattice, int variant, int* bx, int* by)
 {
-    *bx = lattice == DUGKS_D3Q19 ? 18 : 128;
-    *by = lattice == DUGKS_D3Q19 ? 14 : 1;
+    if (lattice == DUGKS_D3Q19) {
+        *bx = 18;
+        *by = 14;
+        return;
+    }
+    *bx = variant == 1 ? 64 : (variant == 2 ? 256 : 128);
+    *by = 1;
 }
 
-hipError_t batch_step_launch(int lattice, int dtype, const void* insts, const long long* bstart, const BatchGeom* geom,
-                             int n, long long nblocks, const void* fin, const void* forces, void* fout,
-                             const long long* step0, int step, hipStream_t st)
+hipError_t batch_step_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
+                             const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
+                             void* fout, const long long* step0, int step, hipStream_t st)
 {
-    if (lattice == DUGKS_D2Q9)
-        return dtype == DUGKS_F64
-                   ? batch_launch_t<D2Q9, double, 128, 1, 2, prefetch_planes<D2Q9, double>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
-                   : batch_launch_t<D2Q9, float, 128, 1, 2, prefetch_planes<D2Q9, float>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
+#define DUGKS_BATCH_ARGS insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st
+    if (lattice == DUGKS_D2Q9) {
+        if (dtype == DUGKS_F64) {
+            if (variant == 1) return batch_launch_t<D2Q9, double, 64, 1, 2, prefetch_planes<D2Q9, double>()>(DUGKS_BATCH_ARGS);
+            if (variant == 2) return batch_launch_t<D2Q9, double, 256, 1, 2, prefetch_planes<D2Q9, double>()>(DUGKS_BATCH_ARGS);
+            return batch_launch_t<D2Q9, double, 128, 1, 2, prefetch_planes<D2Q9, double>()>(DUGKS_BATCH_ARGS);
+        }
+        if (variant == 1) return batch_launch_t<D2Q9, float, 64, 1, 2, prefetch_planes<D2Q9, float>()>(DUGKS_BATCH_ARGS);
+        if (variant == 2) return batch_launch_t<D2Q9, float, 256, 1, 2, prefetch_planes<D2Q9, float>()>(DUGKS_BATCH_ARGS);
+        return batch_launch_t<D2Q9, float, 128, 1, 2, prefetch_planes<D2Q9, float>()>(DUGKS_BATCH_ARGS);
+    }
     return dtype == DUGKS_F64
-               ? batch_launch_t<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st)
-               : batch_launch_t<D3Q19, float, 18, 14, 2, prefetch_planes<D3Q19, float>()>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st);
+               ? batch_launch_t<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(DUGKS_BATCH_ARGS)
+               : batch_launch_t<D3Q19, float, 18, 14, 2, prefetch_planes<D3Q19, float>()>(DUGKS_BATCH_ARGS);
+#undef DUGKS_BATCH_ARGS
 }
 
 }  // namespace dugks

@@ -124,3 +124,27 @@ def test_batch_rejects_mixed_lattices():
     with pytest.raises(M.DugksError) as ei:
         M.BatchSolver([a, b])
     assert ei.value.code == M.EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tuned_batch_equals_untuned(dtype):
+    # the autotuner only changes the tiling and march chunk: the states stay
+    # bitwise equal, and the batch clock (time-dependent forcing) is kept
+    cfgs, forces = make_set(dtype, count=8)
+    say(f"[batch tune] {dtype}")
+    Bt = M.BatchSolver(cfgs, forces=forces)
+    Bu = M.BatchSolver(cfgs, forces=forces)
+    try:
+        Bt.run(3)
+        Bu.run(3)
+        tile, chunk = Bt.tune(nsteps=2)
+        say(f"  chose tile variant {tile}, chunk {chunk}")
+        assert tile in (0, 1, 2) and chunk in (4, 8, 16, 32, 64)
+        Bt.run(4, use_graph=True)
+        Bu.run(4, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(cfgs)):
+            assert torch.equal(Bt.state(i), Bu.state(i)), f"instance {i}"
+    finally:
+        Bt.close()
+        Bu.close()
