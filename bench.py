@@ -251,7 +251,8 @@ def summarize_counters(fetch_dir, write_dir, workload):
         return list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
 
     def per_dispatch(rs, name):
-        step = [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == name and "k_fused2<" in r["Kernel_Name"]]
+        step = [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == name and
+                ("k_fused2<" in r["Kernel_Name"] or "k_split<" in r["Kernel_Name"])]
         copy = [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]
                 and int(r["Grid_Size"]) >= 65536]
         return step, copy
@@ -356,7 +357,7 @@ def main():
         "data": "synthetic (cavity from rest, no external data)",
         "config": {"workload": workload, "cells": cells, "Q": Q, "global_batch": 1, "seq_len": args.n,
                    "parallelism": "single GPU", "dt": cfg["dt"], "tau": cfg["tau"],
-                   "kernel": {0: "general", 1: "fused-twice", 2: "fused"}.get(variant, str(variant))},
+                   "kernel": {0: "general", 1: "fused-twice", 2: "fused", 3: "fused-split"}.get(variant, str(variant))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_step},

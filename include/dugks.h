@@ -193,7 +193,10 @@ int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, 
 /* Which step kernel the context uses (diagnostics): 0 = general two-pass
  * kernels, 1 = fused single launch with every interface evaluated by both
  * neighbouring cells, 2 = fused single launch with every interface
- * evaluated once (default). */
+ * evaluated once, 3 = as 2 with the velocity set split over two lanes per
+ * column.  Default: 3 for D3Q19 FP64 and D2Q9 FP32, 2 otherwise (the
+ * faster one on MI355X); the batched step uses the same kernel as the
+ * default.  All give the same results to rounding. */
 int dugks_kernel_variant(const dugks_ctx* ctx);
 
 /*

@@ -18,6 +18,7 @@
 
 #include "ctx.hpp"
 #include "kernels_general.hpp"
+#include "march.hpp"
 
 namespace dugks {
 
@@ -48,20 +49,6 @@ struct LdsPhi {
     }
     __device__ __forceinline__ T get(int q, int b) const { return s[b + q * SQ]; }
 };
-
-__device__ __forceinline__ int ring(int p) { return ((p % 3) + 3) % 3; }
-
-// metric coefficients of column coordinate x along in-plane axis a (clamped
-// for halo columns, which never update)
-template <typename T>
-__device__ __forceinline__ CellMetric<T> upd_col_pre(const Inst<T>& P, int a, int x)
-{
-    const int i = x < 0 ? 0 : (x >= P.n[a] ? P.n[a] - 1 : x);
-    return load_metric(P, a, i);
-}
-
-// kinds of a column coordinate along one in-plane axis
-enum { COL_CELL = 0, COL_GHOST_LO = 1, COL_GHOST_HI = 2, COL_OUT = 3 };
 
 // One workgroup's work: tile index `tile` (of tiles0 x tiles1) and march
 // chunk `ck` of the instance P; fin/fout/force already point at the
@@ -223,19 +210,6 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restric
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     fused_body<LAT, T, BX, BY>(P, fin, force, fout, gt, gth, chunk, tiles0, blockIdx.x, blockIdx.y,
                                reinterpret_cast<T*>(smem_raw));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Renumber them so that each XCD receives one contiguous range of the
-// logical order (tiles fastest): tiles that share halo columns then run on
-// the same XCD at about the same time and read the shared lines from one L2.
-// A bijection on [0, nb) for any nb.
-__device__ __forceinline__ int xcd_order(int b, int nb)
-{
-    constexpr int X = 8;
-    const int q = nb / X, r = nb % X;
-    const int x = b % X, k = b / X;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
 // ---------------------------------------------------------------------------
@@ -493,8 +467,10 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
     }
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
-__global__ __launch_bounds__(BX* BY, MINW) void k_fused2(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
+// FF: the launch carries a force field (without one the kernel is compiled
+// with a null field and no field code)
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+__global__ DUGKS_KERNEL_BOUNDS(BX * BY, MINW, (max_waves_per_eu<LAT, T, false>())) void k_fused2(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
                                                           const T* __restrict__ force, T* __restrict__ fout,
                                                           double t, int chunk, int tiles0, int tiles)
 {
@@ -503,7 +479,7 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused2(const Inst<T>* __restri
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int ntile = (int)tiles;
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    fused2_body<LAT, T, BX, BY, PF>(P, fin, force, fout, gt, gth, chunk, tiles0, b % ntile, b / ntile,
+    fused2_body<LAT, T, BX, BY, PF>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % ntile, b / ntile,
                                 reinterpret_cast<T*>(smem_raw));
 }
 
@@ -512,8 +488,8 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused2(const Inst<T>* __restri
 // state offset, force offset, tile counts and chunk (BatchGeom).  Time of
 // instance i at this launch: (step0 + step) * dt_i, with step0 a device
 // counter so that a captured graph replays with advancing time.
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
-__global__ __launch_bounds__(BX* BY, MINW) void k_fused2_batch(const Inst<T>* __restrict__ insts,
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+__global__ DUGKS_KERNEL_BOUNDS(BX * BY, MINW, (max_waves_per_eu<LAT, T, false>())) void k_fused2_batch(const Inst<T>* __restrict__ insts,
                                                                 const long long* __restrict__ bstart,
                                                                 const BatchGeom* __restrict__ geom, int ninst,
                                                                 const T* __restrict__ fin, const T* __restrict__ forces,
@@ -534,7 +510,7 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused2_batch(const Inst<T>* __
     const int ntile = g.tiles0 * g.tiles1;
     const double t = (double)(*step0 + step) * P.dtd;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
-    const T* force = (forces && P.foff >= 0) ? forces + P.foff : nullptr;
+    const T* force = (FF && forces && P.foff >= 0) ? forces + P.foff : nullptr;
     fused2_body<LAT, T, BX, BY, PF>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
                                     local / ntile, reinterpret_cast<T*>(smem_raw));
 }
@@ -584,16 +560,16 @@ static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     return hip_check(ctx, hipGetLastError(), "fused step launch");
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
-static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
-                         hipStream_t st, int chunk)
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+static int launch_fused2_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force,
+                            double t, hipStream_t st, int chunk)
 {
     constexpr int D = LAT::D, M = D - 1;
     const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
     const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = fused2_lds<LAT, T, BX, BY>();
-    auto kern = k_fused2<LAT, T, BX, BY, MINW, PF>;
+    auto kern = k_fused2<LAT, T, BX, BY, MINW, PF, FF>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -605,6 +581,14 @@ static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
                        (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0, tiles0 * tiles1);
     return hip_check(ctx, hipGetLastError(), "fused step launch");
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
+static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
+                         hipStream_t st, int chunk)
+{
+    if (force) return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, true>(ctx, P, fin, fout, force, t, st, chunk);
+    return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, false>(ctx, P, fin, fout, force, t, st, chunk);
 }
 
 // tile shapes: D3Q19 18x14 columns (16x12 interior), D2Q9 rows of 128
@@ -624,15 +608,30 @@ static int pick_chunk(const dugks_ctx* ctx)
     return std::min(chunk, std::max(nM, 1));
 }
 
+// Default step kernel per lattice and precision (measured on MI355X, 128^3
+// D3Q19 and 1024^2 D2Q9 cavities): the two-lane split doubles the waves per
+// SIMD where one lane per column runs a single wave (D3Q19 FP64: 155 KB of
+// LDS per tile) and pays its duplicated per-column work elsewhere.
+int default_step_kernel(int lattice, int dtype)
+{
+    if (lattice == DUGKS_D3Q19) return dtype == DUGKS_F64 ? 3 : 2;
+    return dtype == DUGKS_F64 ? 2 : 3;
+}
+
+int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk);
+
 int setup_fast(dugks_ctx* ctx)
 {
     ctx->fast = 0;
     const char* env = getenv("DUGKS_FORCE_GENERAL");
     if (env && env[0] == '1') return DUGKS_OK;
-    // 1: every face evaluated by both neighbours; 2: faces evaluated once
-    ctx->fast = 2;
+    // 1: every face evaluated by both neighbours; 2: faces evaluated once;
+    // 3: faces once, velocity set split over two lanes per column
+    ctx->fast = default_step_kernel(ctx->cfg.lattice, ctx->cfg.dtype);
     const char* v = getenv("DUGKS_FUSED_VARIANT");
     if (v && v[0] == '1') ctx->fast = 1;
+    if (v && v[0] == '2') ctx->fast = 2;
+    if (v && v[0] == '3') ctx->fast = 3;
     // march length override (tuning sweeps)
     const char* ch = getenv("DUGKS_CHUNK");
     ctx->chunk = ch ? std::max(0, atoi(ch)) : 0;
@@ -642,9 +641,10 @@ int setup_fast(dugks_ctx* ctx)
 int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, bool* handled)
 {
     *handled = false;
-    if (ctx->fast != 1 && ctx->fast != 2) return DUGKS_OK;
+    if (ctx->fast < 1 || ctx->fast > 3) return DUGKS_OK;
     *handled = true;
     const int chunk = pick_chunk(ctx);
+    if (ctx->fast == 3) return split_step(ctx, fin, fout, force, t, st, chunk);
     if (ctx->fast == 2) {
         if (ctx->cfg.lattice == DUGKS_D3Q19) {
             if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
@@ -663,25 +663,6 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
 
 void release_fast(dugks_ctx*) {}
 
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
-static hipError_t batch_launch_t(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
-                                 long long nblocks, const void* fin, const void* forces, void* fout,
-                                 const long long* step0, int step, hipStream_t st)
-{
-    auto kern = k_fused2_batch<LAT, T, BX, BY, MINW, PF>;
-    const size_t lds = fused2_lds<LAT, T, BX, BY>();
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(BX * BY), lds, st, (const Inst<T>*)insts, bstart, geom, n,
-                       (const T*)fin, (const T*)forces, (T*)fout, step0, step);
-    return hipGetLastError();
-}
-
 // Tile shapes of the batched kernel: (columns along x, along y) incl. halo.
 // D3Q19 has one (18 x 14: the FP64 LDS ring fills a CU); D2Q9 rows of 128
 // (default), 64 or 256 columns, chosen per batch by the autotuner.
@@ -698,24 +679,65 @@ void fused_tile_shape(int lattice, int variant, int* bx, int* by)
     *by = 1;
 }
 
+
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+static hipError_t fused2_batch_ff(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
+                                  long long nblocks, const void* fin, const void* forces, void* fout,
+                                  const long long* step0, int step, hipStream_t st)
+{
+    auto kern = k_fused2_batch<LAT, T, BX, BY, MINW, PF, FF>;
+    const size_t lds = fused2_lds<LAT, T, BX, BY>();
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(BX * BY), lds, st, (const Inst<T>*)insts, bstart, geom, n,
+                       (const T*)fin, (const T*)forces, (T*)fout, step0, step);
+    return hipGetLastError();
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+static hipError_t fused2_batch_t(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
+                                 long long nblocks, const void* fin, const void* forces, void* fout,
+                                 const long long* step0, int step, hipStream_t st)
+{
+    constexpr bool PF = prefetch_planes<LAT, T>();
+    if (forces)
+        return fused2_batch_ff<LAT, T, BX, BY, MINW, PF, true>(insts, bstart, geom, n, nblocks, fin, forces, fout,
+                                                               step0, step, st);
+    return fused2_batch_ff<LAT, T, BX, BY, MINW, PF, false>(insts, bstart, geom, n, nblocks, fin, forces, fout, step0,
+                                                            step, st);
+}
+
+hipError_t split_batch_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
+                              const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
+                              void* fout, const long long* step0, int step, hipStream_t st);
+
+// one batched step on the default step kernel of the lattice and precision
+// (so that batched and single-instance runs give identical states)
 hipError_t batch_step_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
                              const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
                              void* fout, const long long* step0, int step, hipStream_t st)
 {
+    if (default_step_kernel(lattice, dtype) == 3)
+        return split_batch_launch(lattice, dtype, variant, insts, bstart, geom, n, nblocks, fin, forces, fout, step0,
+                                  step, st);
 #define DUGKS_BATCH_ARGS insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st
     if (lattice == DUGKS_D2Q9) {
         if (dtype == DUGKS_F64) {
-            if (variant == 1) return batch_launch_t<D2Q9, double, 64, 1, 2, prefetch_planes<D2Q9, double>()>(DUGKS_BATCH_ARGS);
-            if (variant == 2) return batch_launch_t<D2Q9, double, 256, 1, 2, prefetch_planes<D2Q9, double>()>(DUGKS_BATCH_ARGS);
-            return batch_launch_t<D2Q9, double, 128, 1, 2, prefetch_planes<D2Q9, double>()>(DUGKS_BATCH_ARGS);
+            if (variant == 1) return fused2_batch_t<D2Q9, double, 64, 1, 2>(DUGKS_BATCH_ARGS);
+            if (variant == 2) return fused2_batch_t<D2Q9, double, 256, 1, 2>(DUGKS_BATCH_ARGS);
+            return fused2_batch_t<D2Q9, double, 128, 1, 2>(DUGKS_BATCH_ARGS);
         }
-        if (variant == 1) return batch_launch_t<D2Q9, float, 64, 1, 2, prefetch_planes<D2Q9, float>()>(DUGKS_BATCH_ARGS);
-        if (variant == 2) return batch_launch_t<D2Q9, float, 256, 1, 2, prefetch_planes<D2Q9, float>()>(DUGKS_BATCH_ARGS);
-        return batch_launch_t<D2Q9, float, 128, 1, 2, prefetch_planes<D2Q9, float>()>(DUGKS_BATCH_ARGS);
+        if (variant == 1) return fused2_batch_t<D2Q9, float, 64, 1, 2>(DUGKS_BATCH_ARGS);
+        if (variant == 2) return fused2_batch_t<D2Q9, float, 256, 1, 2>(DUGKS_BATCH_ARGS);
+        return fused2_batch_t<D2Q9, float, 128, 1, 2>(DUGKS_BATCH_ARGS);
     }
-    return dtype == DUGKS_F64
-               ? batch_launch_t<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(DUGKS_BATCH_ARGS)
-               : batch_launch_t<D3Q19, float, 18, 14, 2, prefetch_planes<D3Q19, float>()>(DUGKS_BATCH_ARGS);
+    return dtype == DUGKS_F64 ? fused2_batch_t<D3Q19, double, 18, 14, 1>(DUGKS_BATCH_ARGS)
+                              : fused2_batch_t<D3Q19, float, 18, 14, 2>(DUGKS_BATCH_ARGS);
 #undef DUGKS_BATCH_ARGS
 }
 

@@ -1,0 +1,711 @@
+// kernels_split.hip -- the fused single-launch step with the velocity set
+// split over two lanes per column.
+//
+// The march is that of the faces-once fused kernel (an LDS ring of three
+// f-bar-plus planes, every interface evaluated once, x/y face values
+// exchanged through LDS, the march-axis face carried in registers), but each
+// column is served by two lanes of one wavefront, l and l^32.  Lane half 0
+// owns the velocities q = 0..K-1 (K = index of the rest velocity) and the
+// rest velocity; half 1 owns their opposites Q-1-k, whose components are
+// -e(k) and whose weights are equal.  All per-velocity work (Eq. f_bar_+,
+// reconstruction, equilibria, source, wall rules, fluxes, update) is done by
+// the owning lane from the half-0 velocity table with the sign sigma = +-1
+// folded into u, G and the xi-weighted coefficients; the velocity moments of
+// cells and interfaces are partial sums added across the two lanes.  The
+// halves of a column always take the same branches, so both partners of an
+// exchange are active.  Halving the per-thread state and doubling the
+// threads per tile raises occupancy at the same LDS footprint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ctx.hpp"
+#include "kernels_general.hpp"
+#include "march.hpp"
+
+namespace dugks {
+
+
+// value of the partner lane (same column, other half)
+template <typename T>
+__device__ __forceinline__ T partner(T v)
+{
+    return __shfl_xor(v, 32);
+}
+
+// number of half-0 velocities crossing a face of axis A, and the slot of k
+template <class LAT, int A>
+__host__ __device__ constexpr int half_cross_slot(int k)
+{
+    int s = 0;
+    for (int r = 0; r < k; ++r)
+        if (LAT::e(r, A) != 0) ++s;
+    return s;
+}
+template <class LAT, int A>
+__host__ __device__ constexpr int half_cross_count()
+{
+    return half_cross_slot<LAT, A>(LAT::REST);
+}
+
+// f-bar-plus in the LDS ring.  Slot layout of one plane: half-0 velocities
+// k = 0..K-1 in slots 0..K-1, the rest velocity in slot K, half-1 velocities
+// in slots K+1..2K; every slot is a BX x BY array of columns.
+template <class LAT, typename T, int BX, int BY>
+struct HalfPhi {
+    const T* s;
+    int cur;           // element offset of (current plane, slot 0, this column)
+    int hb;            // element offset of this lane's first slot
+    int dz_up, dz_dn;  // offset from the current plane to the next / previous
+    static constexpr int SQ = BX * BY;
+    __device__ __forceinline__ int base(int ox, int oy, int oz) const
+    {
+        if constexpr (LAT::D == 3) return cur + ox + oy * BX + (oz > 0 ? dz_up : (oz < 0 ? dz_dn : 0));
+        else return cur + ox + (oy > 0 ? dz_up : (oy < 0 ? dz_dn : 0));
+    }
+    __device__ __forceinline__ int up(int t) const
+    {
+        if constexpr (LAT::D == 3) return t == 0 ? 1 : (t == 1 ? BX : dz_up);
+        else return t == 0 ? 1 : dz_up;
+    }
+    __device__ __forceinline__ int dn(int t) const
+    {
+        if constexpr (LAT::D == 3) return t == 0 ? 1 : (t == 1 ? BX : -dz_dn);
+        else return t == 0 ? 1 : -dz_dn;
+    }
+    __device__ __forceinline__ T get(int k, int b) const { return s[b + hb + k * SQ]; }
+    __device__ __forceinline__ T rest(int b) const { return s[b + LAT::REST * SQ]; }
+};
+
+// cell moments and f-bar-plus (Appendix step 1, Eq. f_bar_+) of the lane's
+// velocities; fv: lane velocities, fr: rest velocity (both lanes hold it)
+template <class LAT, typename T>
+__device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::REST], T fr, const T (&fg)[3],
+                                         bool has_field, T gt, T sg, T (&out)[LAT::REST], T& orest)
+{
+    constexpr int K = LAT::REST, D = LAT::D;
+    const T invRT = T(1) / P.RT;
+    T rh = T(0), sj[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        rh += fv[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (LAT::e(k, a) == 1) sj[a] += fv[k];
+            if (LAT::e(k, a) == -1) sj[a] -= fv[k];
+        }
+    }
+    const T rho = (rh + partner(rh)) + fr;
+    T G[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)}, us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const T jh = sg * sj[a];
+        const T j = jh + partner(jh);
+        G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
+        u[a] = P.c * j / P.rho0 + P.h * G[a];
+        us[a] = sg * u[a];
+        Gs[a] = sg * G[a];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const T fe = feq_q<LAT, T>(k, rho, us, P.rho0, P.c, invRT);
+        const T S = src_fac<LAT, T>(k, us, Gs, P.c, invRT) * fe;
+        out[k] = fv[k] + P.B1 * (fe - fv[k]) + P.C1 * S;
+    }
+    const T fe = feq_q<LAT, T>(LAT::REST, rho, u, P.rho0, P.c, invRT);
+    const T S = src_fac<LAT, T>(LAT::REST, u, G, P.c, invRT) * fe;
+    orest = fr + P.B1 * (fe - fr) + P.C1 * S;
+}
+
+// Appendix steps 3-4 for the lane's velocities on the interface of axis A
+// between the cells at offsets off and off+1 (weight w of the right cell,
+// normal-difference scale gn); the rest velocity (no gradient term) too
+template <class LAT, typename T, class ACC, int A>
+__device__ __forceinline__ void recon_half(const Inst<T>& P, const ACC& ph, int off, T w, T gn,
+                                           const CellMetric<T>& mx, const CellMetric<T>& my,
+                                           const CellMetric<T>& mz, T sg, T (&out)[LAT::REST], T& orest)
+{
+    constexpr int K = LAT::REST, D = LAT::D;
+    const int bL = ph.base(A == 0 ? off : 0, A == 1 ? off : 0, A == 2 ? off : 0);
+    const int bR = ph.base(A == 0 ? off + 1 : 0, A == 1 ? off + 1 : 0, A == 2 ? off + 1 : 0);
+    const T hcg = sg * (P.h * P.c * gn);
+    const T hc = sg * (P.h * P.c);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const T pL = ph.get(k, bL), pR = ph.get(k, bR);
+        T v = pL + w * (pR - pL);
+        if (LAT::e(k, A) != 0) v -= T(LAT::e(k, A)) * hcg * (pR - pL);
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            if (t == A || LAT::e(k, t) == 0) continue;
+            const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
+            const int u = ph.up(t), d = ph.dn(t);
+            const T dL = mt.cp * ph.get(k, bL + u) + mt.c0 * pL + mt.cm * ph.get(k, bL - d);
+            const T dR = mt.cp * ph.get(k, bR + u) + mt.c0 * pR + mt.cm * ph.get(k, bR - d);
+            v -= T(LAT::e(k, t)) * hc * (dL + w * (dR - dL));
+        }
+        out[k] = v;
+    }
+    const T rL = ph.rest(bL), rR = ph.rest(bR);
+    orest = rL + w * (rR - rL);
+}
+
+// interface moments (Appendix step 6) from the two lanes' values
+template <class LAT, typename T>
+__device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
+                                             T& rho, T* u)
+{
+    constexpr int K = LAT::REST, D = LAT::D;
+    T rh = T(0), sj[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        rh += fb[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (LAT::e(k, a) == 1) sj[a] += fb[k];
+            if (LAT::e(k, a) == -1) sj[a] -= fb[k];
+        }
+    }
+    rho = (rh + partner(rh)) + fr;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const T jh = sg * sj[a];
+        u[a] = P.c * (jh + partner(jh)) / P.rho0 + T(0.5) * P.h * G[a];
+    }
+}
+
+// what the NEQ rule needs from the opposite interface of a wall cell
+template <class LAT, typename T>
+struct NeqHalf {
+    T rc, uc[3];
+    T neq[LAT::REST];
+};
+
+template <class LAT, typename T, int A>
+__device__ __forceinline__ void neq_capture_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
+                                                 NeqHalf<LAT, T>& I)
+{
+    const T invRT = T(1) / P.RT;
+    moments_half<LAT, T>(P, fb, fr, G, sg, I.rc, I.uc);
+    T us[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < LAT::D; ++a) us[a] = sg * I.uc[a];
+#pragma unroll
+    for (int k = 0; k < LAT::REST; ++k) {
+        if (LAT::e(k, A) == 0) continue;
+        I.neq[k] = fb[k] - feq_q<LAT, T>(k, I.rc, us, P.rho0, P.c, invRT);
+    }
+}
+
+// Appendix step 5 on a wall face of side s = 2A + (sgs > 0) (Eqs. BB, NEQ)
+// for the lane's velocities entering the domain (sigma e_A sgs < 0)
+template <class LAT, typename T, int A>
+__device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&wall)[LAT::REST],
+                                          const NeqHalf<LAT, T>& I, T sg, int sgi)
+{
+    constexpr int K = LAT::REST, D = LAT::D;
+    const T invRT = T(1) / P.RT;
+    const int kind = P.bc[s];
+    if (kind == BC_BOUNCE_BACK) {
+        T other[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (LAT::e(k, A) != 0) other[k] = partner(wall[k]);  // opposite velocity, before the rule
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (LAT::e(k, A) == 0) continue;
+            if (sgi * LAT::e(k, A) * sgs >= 0) continue;
+            T xu = T(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) xu += xi_of<LAT, T>(k, d, P.c) * P.uw[s][d];
+            wall[k] = other[k] + T(2) * P.rho0 * T(LAT::w(k)) * (sg * xu) * invRT;
+        }
+        return;
+    }
+    T ra, ua[3] = {T(0), T(0), T(0)};
+    if (kind == BC_NEQ_VELOCITY) {
+        ra = I.rc;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ua[d] = sg * P.uw[s][d];
+    } else {
+        ra = P.rhow[s];
+#pragma unroll
+        for (int d = 0; d < D; ++d) ua[d] = sg * I.uc[d];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (LAT::e(k, A) == 0) continue;
+        if (sgi * LAT::e(k, A) * sgs >= 0) continue;
+        wall[k] = feq_q<LAT, T>(k, ra, ua, P.rho0, P.c, invRT) + I.neq[k];
+    }
+}
+
+// The interface of axis A with index f between the cells at offsets off and
+// off+1: steps 3-7 for the lane's velocities; out[half_cross_slot] receives
+// f (step 7) of the lane's velocities crossing the face.
+template <class LAT, typename T, class ACC, int A>
+__device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
+                                          int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
+                                          const CellMetric<T>& mz, T sg, int sgi, T* out)
+{
+    constexpr int K = LAT::REST;
+    const AxisMetric<T>& m = P.m[A];
+    const int n = P.n[A];
+    const bool wall_lo = !P.per[A] && f == 0;
+    const bool wall_hi = !P.per[A] && f == n;
+    const T invRT = T(1) / P.RT;
+    NeqHalf<LAT, T> info;
+    asm volatile("" ::: "memory");
+    T fb[K], fr, G[3];
+    if (wall_lo || wall_hi) {
+        const int fo = wall_lo ? 1 : n - 1;
+        const int oo = wall_lo ? off + 1 : off - 1;
+        recon_half<LAT, T, ACC, A>(P, ph, oo, m.w[fo], m.gn[fo], mx, my, mz, sg, fb, fr);
+        face_force<LAT, T>(P, force, A, fo, m.w[fo], ci, gth, G);
+        neq_capture_half<LAT, T, A>(P, fb, fr, G, sg, info);
+        asm volatile("" ::: "memory");
+    }
+    const T w = m.w[f];
+    recon_half<LAT, T, ACC, A>(P, ph, off, w, m.gn[f], mx, my, mz, sg, fb, fr);
+    face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
+    if (wall_lo) wall_half<LAT, T, A>(P, 2 * A, -1, fb, info, sg, sgi);
+    if (wall_hi) wall_half<LAT, T, A>(P, 2 * A + 1, 1, fb, info, sg, sgi);
+    T rho, u[3];
+    moments_half<LAT, T>(P, fb, fr, G, sg, rho, u);
+    T us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < LAT::D; ++a) {
+        us[a] = sg * u[a];
+        Gs[a] = sg * G[a];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (LAT::e(k, A) == 0) continue;
+        const T fe = feq_q<LAT, T>(k, rho, us, P.rho0, P.c, invRT);
+        const T S = src_fac<LAT, T>(k, us, Gs, P.c, invRT) * fe;
+        out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]) + P.C7 * S;  // step 7
+    }
+}
+
+// Threads of a tile: 2 x NCOL, NCOL = BX*BY rounded up to whole half-waves.
+template <int BX, int BY>
+__host__ __device__ constexpr int split_threads()
+{
+    return 2 * ((BX * BY + 31) / 32) * 32;
+}
+
+// One workgroup's work: tile `tile` (of tiles0 x tiles1) and march chunk
+// `ck` of instance P; fin/fout/force point at the instance's arrays.
+template <class LAT, typename T, int BX, int BY, bool PF>
+__device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
+                                           T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
+                                           int ck, T* lds)
+{
+    constexpr int Q = LAT::Q, D = LAT::D, M = D - 1, K = LAT::REST;
+    constexpr int NX = half_cross_count<LAT, 0>(), NY = half_cross_count<LAT, 1>();
+    constexpr int NM = half_cross_count<LAT, M>();
+    constexpr int SQ = BX * BY;
+    T* fxb = lds + 3 * Q * SQ;   // [2][NX][BY][BX] upper x faces, per half
+    T* fyb = fxb + 2 * NX * SQ;  // [2][NY][BY][BX] upper y faces (3-D)
+    const int tid = threadIdx.x;
+    const int h = (tid >> 5) & 1;
+    const int col = (tid >> 6) * 32 + (tid & 31);
+    const bool in_tile = col < SQ;
+    const int tx = in_tile ? col % BX : 0, ty = in_tile ? col / BX : 0;
+    const T sg = h ? T(-1) : T(1);
+    const int sgi = h ? -1 : 1;
+    const int hs = h ? K + 1 : 0;  // first LDS slot of this lane
+    const int b0 = tile % tiles0, b1 = tile / tiles0;
+
+    int g[2], kind[2], src[2];
+    g[0] = b0 * (BX - 2) - 1 + tx;
+    g[1] = (D == 3) ? b1 * (BY - 2) - 1 + ty : 0;
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) {
+        const int N = P.n[a], x = g[a];
+        if (!in_tile) { kind[a] = COL_OUT; src[a] = 0; }
+        else if (x >= 0 && x < N) { kind[a] = COL_CELL; src[a] = x; }
+        else if (P.per[a] && x == -1) { kind[a] = COL_CELL; src[a] = N - 1; }
+        else if (P.per[a] && x == N) { kind[a] = COL_CELL; src[a] = 0; }
+        else if (!P.per[a] && x == -1) { kind[a] = COL_GHOST_LO; src[a] = 0; }
+        else if (!P.per[a] && x == N) { kind[a] = COL_GHOST_HI; src[a] = N - 1; }
+        else { kind[a] = COL_OUT; src[a] = 0; }
+    }
+    if (D == 2) { kind[1] = in_tile ? COL_CELL : COL_OUT; src[1] = 0; }
+    const bool cell_col = kind[0] == COL_CELL && kind[1] == COL_CELL;
+    const bool ghost_col = !cell_col && kind[0] != COL_OUT && kind[1] != COL_OUT;
+    const bool row_ok = in_tile && ((D == 2) || (g[1] >= 0 && g[1] < P.n[1] && ty >= 1 && ty <= BY - 2));
+    const bool col_ok = in_tile && g[0] >= 0 && g[0] < P.n[0] && tx >= 1 && tx <= BX - 2;
+    const bool upd_col = cell_col && col_ok && row_ok;
+    const bool xface = (cell_col || ghost_col) && row_ok && tx <= BX - 2 && g[0] >= -1 && g[0] <= P.n[0] - 1;
+    const bool yface = (D == 3) && (cell_col || ghost_col) && col_ok && ty <= BY - 2 && g[1] >= -1 &&
+                       g[1] <= P.n[1] - 1;
+
+    const bool any_ghost = __syncthreads_or(ghost_col) != 0;
+    const int nM = P.n[M];
+    const int p0 = ck * chunk;
+    const int p1 = min(p0 + chunk, nM);
+    const bool perM = P.per[M] != 0;
+    const CellMetric<T> cmx = upd_col_pre(P, 0, g[0]);
+    const CellMetric<T> cmy = D == 3 ? upd_col_pre(P, 1, g[1]) : cmx;
+    // global element offsets of the lane's velocities: q = k (half 0) or
+    // Q-1-k (half 1)
+    const long long q0off = h ? (long long)(Q - 1) * P.nc : 0;
+    const long long qstep = h ? -P.nc : P.nc;
+    const long long roff = (long long)LAT::REST * P.nc;
+
+    // element of (plane p, slot s, this column + (dx, dy))
+    auto lds_el = [&](int p, int s, int dx, int dy) -> int { return ((ring(p) * Q + s) * BY + ty + dy) * BX + tx + dx; };
+
+    T pf[K], prest = T(0), pg[3] = {T(0), T(0), T(0)};
+    auto plane_cell = [&](int p) -> long long {
+        const int pp = perM ? ((p % nM) + nM) % nM : p;
+        return int_idx(P, src[0], (D == 3) ? src[1] : pp, (D == 3) ? pp : 0);
+    };
+    auto load_plane = [&](int p) {
+        if (cell_col) {
+            const long long ci = plane_cell(p);
+            const T* fp = fin + ci + q0off;
+#pragma unroll
+            for (int k = 0; k < K; ++k) pf[k] = fp[k * qstep];
+            prest = fin[ci + roff];
+            if (force) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) pg[a] = force[(long long)a * P.nc + ci];
+            }
+        }
+    };
+    auto compute_plane = [&](int p) {
+        if (cell_col) {
+            T v[K], vr;
+            phi_half<LAT, T>(P, pf, prest, pg, force != nullptr, gt, sg, v, vr);
+#pragma unroll
+            for (int k = 0; k < K; ++k) lds[lds_el(p, hs + k, 0, 0)] = v[k];
+            if (h == 0) lds[lds_el(p, K, 0, 0)] = vr;
+        }
+        __syncthreads();
+        if (!any_ghost) return;
+        if (ghost_col) {
+            int off[2][2];
+            T wt[2][2];
+            int cnt[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                cnt[a] = 1;
+                off[a][0] = 0; wt[a][0] = T(1);
+                off[a][1] = 0; wt[a][1] = T(0);
+                if (a < D - 1 && kind[a] == COL_GHOST_LO) {
+                    cnt[a] = 2;
+                    off[a][0] = 1; wt[a][0] = T(1) - P.rlo[a];
+                    off[a][1] = 2; wt[a][1] = P.rlo[a];
+                } else if (a < D - 1 && kind[a] == COL_GHOST_HI) {
+                    cnt[a] = 2;
+                    off[a][0] = -1; wt[a][0] = T(1) - P.rhi[a];
+                    off[a][1] = -2; wt[a][1] = P.rhi[a];
+                }
+            }
+            T acc[K + 1];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) acc[k] = T(0);
+            for (int i1 = 0; i1 < cnt[1]; ++i1)
+                for (int i0 = 0; i0 < cnt[0]; ++i0) {
+                    const T w = wt[0][i0] * wt[1][i1];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) acc[k] += w * lds[lds_el(p, hs + k, off[0][i0], off[1][i1])];
+                    acc[K] += w * lds[lds_el(p, K, off[0][i0], off[1][i1])];
+                }
+#pragma unroll
+            for (int k = 0; k < K; ++k) lds[lds_el(p, hs + k, 0, 0)] = acc[k];
+            if (h == 0) lds[lds_el(p, K, 0, 0)] = acc[K];
+        }
+        __syncthreads();
+    };
+    // ghost plane p of a wall march axis: extrapolation through planes a, b
+    auto ghost_plane = [&](int p, int a, int b, T r) {
+        if (cell_col || ghost_col) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                lds[lds_el(p, hs + k, 0, 0)] =
+                    (T(1) - r) * lds[lds_el(a, hs + k, 0, 0)] + r * lds[lds_el(b, hs + k, 0, 0)];
+            if (h == 0)
+                lds[lds_el(p, K, 0, 0)] = (T(1) - r) * lds[lds_el(a, K, 0, 0)] + r * lds[lds_el(b, K, 0, 0)];
+        }
+        __syncthreads();
+    };
+    auto phi_view = [&](int z) {
+        const int slot = Q * SQ;
+        return HalfPhi<LAT, T, BX, BY>{lds, ring(z) * slot + ty * BX + tx, hs * SQ, (ring(z + 1) - ring(z)) * slot,
+                                       (ring(z - 1) - ring(z)) * slot};
+    };
+    auto computed = [&](int p) { return perM || p < nM; };
+
+    int hi;
+    if (!perM && p0 == 0) {
+        load_plane(0);
+        compute_plane(0);
+        load_plane(1);
+        compute_plane(1);
+        ghost_plane(-1, 0, 1, P.rlo[M]);
+        hi = 1;
+    } else {
+        load_plane(p0 - 1);
+        compute_plane(p0 - 1);
+        load_plane(p0);
+        compute_plane(p0);
+        hi = p0;
+    }
+    if (PF && hi + 1 <= p1 && computed(hi + 1)) load_plane(hi + 1);
+    // lower march-axis face of the first plane
+    T zlo[NM > 0 ? NM : 1];
+    if (upd_col) {
+        int ci[3];
+        ci[0] = g[0];
+        ci[1] = (D == 3) ? g[1] : p0;
+        ci[2] = (D == 3) ? p0 : 0;
+        const CellMetric<T> cmm = load_metric(P, M, p0);
+        const auto ph = phi_view(p0);
+        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
+        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
+    }
+    for (int z = p0; z < p1; ++z) {
+        if (hi < z + 1) {
+            __syncthreads();  // ring slot of z+1 and the face buffers were read by the last update
+            if (!computed(z + 1)) {
+                ghost_plane(z + 1, z, z - 1, P.rhi[M]);
+            } else {
+                if (!PF) load_plane(z + 1);
+                compute_plane(z + 1);
+            }
+            hi = z + 1;
+            if (PF && z + 2 <= p1 && computed(z + 2)) load_plane(z + 2);
+        } else {
+            __syncthreads();
+        }
+        int ci[3];
+        ci[0] = g[0];
+        ci[1] = (D == 3) ? g[1] : z;
+        ci[2] = (D == 3) ? z : 0;
+        const CellMetric<T> cmm = load_metric(P, M, z);
+        const auto ph = phi_view(z);
+        // the cell's own state for Eq. (f_tilde_+)
+        T fz[K], fzr = T(0);
+        auto load_own = [&]() {
+            const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+            const T* fp = fin + cidx + q0off;
+#pragma unroll
+            for (int k = 0; k < K; ++k) fz[k] = fp[k * qstep];
+            fzr = fin[cidx + roff];
+        };
+        if (PF && upd_col) load_own();
+        T zhi[NM > 0 ? NM : 1];
+        if (xface) {
+            T v[NX];
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
+#pragma unroll
+            for (int kc = 0; kc < NX; ++kc) fxb[((h * NX + kc) * BY + ty) * BX + tx] = v[kc];
+        }
+        if constexpr (D == 3) {
+            if (yface) {
+                T v[NY];
+                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+#pragma unroll
+                for (int kc = 0; kc < NY; ++kc) fyb[((h * NY + kc) * BY + ty) * BX + tx] = v[kc];
+            }
+        }
+        if (upd_col) {
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
+        }
+        __syncthreads();
+        if (upd_col) {
+            const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+            if (!PF) load_own();
+            T acc[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T p = ph.get(k, ph.cur);
+                acc[k] = p + (p - fz[k]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
+            }
+            const T pr = ph.rest(ph.cur);
+            const T accr = pr + (pr - fzr) * T(1.0 / 3.0);
+            const T sx = sg * (cmx.fdx * P.c), sm = sg * (cmm.fdx * P.c);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (LAT::e(k, 0) != 0) {
+                    const int kc = half_cross_slot<LAT, 0>(k);
+                    const T d = fxb[((h * NX + kc) * BY + ty) * BX + tx] - fxb[((h * NX + kc) * BY + ty) * BX + tx - 1];
+                    acc[k] -= T(LAT::e(k, 0)) * sx * d;
+                }
+                if constexpr (D == 3) {
+                    if (LAT::e(k, 1) != 0) {
+                        const int kc = half_cross_slot<LAT, 1>(k);
+                        const T d = fyb[((h * NY + kc) * BY + ty) * BX + tx] - fyb[((h * NY + kc) * BY + ty - 1) * BX + tx];
+                        acc[k] -= T(LAT::e(k, 1)) * (sg * (cmy.fdx * P.c)) * d;
+                    }
+                }
+                if (LAT::e(k, M) != 0) {
+                    const int kc = half_cross_slot<LAT, M>(k);
+                    acc[k] -= T(LAT::e(k, M)) * sm * (zhi[kc] - zlo[kc]);
+                }
+            }
+            T* fp = fout + cidx + q0off;
+#pragma unroll
+            for (int k = 0; k < K; ++k) fp[k * qstep] = acc[k];
+            if (h == 0) fout[cidx + roff] = accr;
+#pragma unroll
+            for (int kc = 0; kc < NM; ++kc) zlo[kc] = zhi[kc];
+        }
+    }
+}
+
+// FF: the launch carries a force field (without one the kernel is compiled
+// with a null field and no field code)
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+__global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_eu<LAT, T, true>())) void k_split(const Inst<T>* __restrict__ Pp,
+                                                                          const T* __restrict__ fin,
+                                                                          const T* __restrict__ force,
+                                                                          T* __restrict__ fout, double t, int chunk,
+                                                                          int tiles0, int tiles)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Inst<T>& P = *Pp;
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
+    const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    split_body<LAT, T, BX, BY, PF>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % tiles, b / tiles,
+                                   reinterpret_cast<T*>(smem_raw));
+}
+
+// batched form (see k_fused2_batch): workgroup b in XCD order belongs to the
+// instance i with bstart[i] <= b < bstart[i+1]
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+__global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_eu<LAT, T, true>())) void k_split_batch(
+    const Inst<T>* __restrict__ insts, const long long* __restrict__ bstart, const BatchGeom* __restrict__ geom,
+    int ninst, const T* __restrict__ fin, const T* __restrict__ forces, T* __restrict__ fout,
+    const long long* __restrict__ step0, int step)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const long long b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bstart[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const Inst<T>& P = insts[lo];
+    const BatchGeom g = geom[lo];
+    const int local = (int)(b - bstart[lo]);
+    const int ntile = g.tiles0 * g.tiles1;
+    const double t = (double)(*step0 + step) * P.dtd;
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
+    const T* force = (FF && forces && P.foff >= 0) ? forces + P.foff : nullptr;
+    split_body<LAT, T, BX, BY, PF>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
+                                   local / ntile, reinterpret_cast<T*>(smem_raw));
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <class LAT, typename T, int BX, int BY>
+static size_t split_lds()
+{
+    return (size_t)(3 * LAT::Q + 2 * half_cross_count<LAT, 0>() + (LAT::D == 3 ? 2 * half_cross_count<LAT, 1>() : 0)) *
+           BX * BY * sizeof(T);
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+static int launch_split_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
+                           hipStream_t st, int chunk)
+{
+    constexpr int D = LAT::D, M = D - 1;
+    const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
+    const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
+    const int chunks = (P.n[M] + chunk - 1) / chunk;
+    const size_t lds = split_lds<LAT, T, BX, BY>();
+    auto kern = k_split<LAT, T, BX, BY, MINW, PF, FF>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_check(ctx, e, "split kernel LDS attribute");
+        attr_set = true;
+    }
+    const long long nb = (long long)tiles0 * tiles1 * chunks;
+    if (nb > 0x7fffffffLL) return fail(ctx, DUGKS_EUNSUPPORTED, "mesh too large for one launch");
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(split_threads<BX, BY>()), lds, st,
+                       (const Inst<T>*)ctx->inst_dev, (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0,
+                       tiles0 * tiles1);
+    return hip_check(ctx, hipGetLastError(), "split step launch");
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
+static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
+                        hipStream_t st, int chunk)
+{
+    if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true>(ctx, P, fin, fout, force, t, st, chunk);
+    return launch_split_ff<LAT, T, BX, BY, MINW, PF, false>(ctx, P, fin, fout, force, t, st, chunk);
+}
+
+int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk)
+{
+    if (ctx->cfg.lattice == DUGKS_D3Q19) {
+        if (ctx->cfg.dtype == DUGKS_F64)
+            return launch_split<D3Q19, double, 18, 14, 1, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+        return launch_split<D3Q19, float, 18, 14, 2, false>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+    }
+    if (ctx->cfg.dtype == DUGKS_F64)
+        return launch_split<D2Q9, double, 128, 1, 2, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+    return launch_split<D2Q9, float, 128, 1, 2, false>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+static hipError_t split_batch_launch_ff(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
+                                        long long nblocks, const void* fin, const void* forces, void* fout,
+                                        const long long* step0, int step, hipStream_t st)
+{
+    auto kern = k_split_batch<LAT, T, BX, BY, MINW, PF, FF>;
+    const size_t lds = split_lds<LAT, T, BX, BY>();
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(split_threads<BX, BY>()), lds, st, (const Inst<T>*)insts,
+                       bstart, geom, n, (const T*)fin, (const T*)forces, (T*)fout, step0, step);
+    return hipGetLastError();
+}
+
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
+static hipError_t split_batch_launch_t(const void* insts, const long long* bstart, const BatchGeom* geom, int n,
+                                       long long nblocks, const void* fin, const void* forces, void* fout,
+                                       const long long* step0, int step, hipStream_t st)
+{
+    if (forces)
+        return split_batch_launch_ff<LAT, T, BX, BY, MINW, PF, true>(insts, bstart, geom, n, nblocks, fin, forces, fout,
+                                                                     step0, step, st);
+    return split_batch_launch_ff<LAT, T, BX, BY, MINW, PF, false>(insts, bstart, geom, n, nblocks, fin, forces, fout,
+                                                                  step0, step, st);
+}
+
+hipError_t split_batch_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
+                              const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
+                              void* fout, const long long* step0, int step, hipStream_t st)
+{
+#define DUGKS_SPLIT_ARGS insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st
+    if (lattice == DUGKS_D2Q9) {
+        if (dtype == DUGKS_F64) {
+            if (variant == 1) return split_batch_launch_t<D2Q9, double, 64, 1, 2, false>(DUGKS_SPLIT_ARGS);
+            if (variant == 2) return split_batch_launch_t<D2Q9, double, 256, 1, 2, false>(DUGKS_SPLIT_ARGS);
+            return split_batch_launch_t<D2Q9, double, 128, 1, 2, false>(DUGKS_SPLIT_ARGS);
+        }
+        if (variant == 1) return split_batch_launch_t<D2Q9, float, 64, 1, 2, false>(DUGKS_SPLIT_ARGS);
+        if (variant == 2) return split_batch_launch_t<D2Q9, float, 256, 1, 2, false>(DUGKS_SPLIT_ARGS);
+        return split_batch_launch_t<D2Q9, float, 128, 1, 2, false>(DUGKS_SPLIT_ARGS);
+    }
+    return dtype == DUGKS_F64 ? split_batch_launch_t<D3Q19, double, 18, 14, 1, false>(DUGKS_SPLIT_ARGS)
+                              : split_batch_launch_t<D3Q19, float, 18, 14, 2, false>(DUGKS_SPLIT_ARGS);
+#undef DUGKS_SPLIT_ARGS
+}
+
+}  // namespace dugks

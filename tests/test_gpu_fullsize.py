@@ -10,6 +10,7 @@ import pytest
 
 import bench
 import oracle as O
+from tests.test_gpu_parity import default_kernel
 from synthetic import batch_instances, field, perturb
 
 torch = pytest.importorskip("torch")
@@ -40,7 +41,7 @@ def gpu_steps(cfg, f0, nsteps):
     fb = torch.empty_like(fa)
     ctx = M.dugks_init(cfg, fb)
     try:
-        assert M.dugks_kernel_variant(ctx) == 2  # the benchmarked fused kernel
+        assert M.dugks_kernel_variant(ctx) == default_kernel(cfg)  # the benchmarked step kernel
         which = M.dugks_run(ctx, fa, fb, nsteps, None, 0.0)
         torch.cuda.synchronize()
         return (fb if which else fa).double().cpu().numpy()

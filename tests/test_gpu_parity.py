@@ -34,17 +34,27 @@ def to_dev(a, cfg):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=tdt(cfg))
 
 
-VARIANTS = {"general": 0, "fused-twice": 1, "fused": 2}
+VARIANTS = {"general": 0, "fused-twice": 1, "fused": 2, "split": 3}
+
+
+def default_kernel(cfg):
+    """the library's default step kernel (documented in dugks.h)"""
+    f64 = cfg.get("dtype", "f64") == "f64"
+    if cfg["lattice"] == 19:
+        return 3 if f64 else 2
+    return 2 if f64 else 3
 
 
 def make_ctx(cfg, fb, variant=None, **kw):
-    """context on the requested step kernel (None: library default = fused,
-    faces once); 'fused-twice' evaluates every face from both cells"""
+    """context on the requested step kernel (None: the library default);
+    'split' = faces once, velocity set split over two lanes per column;
+    'fused' = faces once, one lane per column; 'fused-twice' evaluates every
+    face from both cells; 'general' = two-kernel path"""
     import os
     keys = ("DUGKS_FORCE_GENERAL", "DUGKS_FUSED_VARIANT")
     old = {k: os.environ.get(k) for k in keys}
     os.environ["DUGKS_FORCE_GENERAL"] = "1" if variant == "general" else "0"
-    os.environ["DUGKS_FUSED_VARIANT"] = "1" if variant == "fused-twice" else "2"
+    os.environ["DUGKS_FUSED_VARIANT"] = {"fused-twice": "1", "fused": "2", "split": "3"}.get(variant, "0")
     try:
         ctx = M.dugks_init(cfg, fb, **kw)
     finally:
@@ -53,7 +63,10 @@ def make_ctx(cfg, fb, variant=None, **kw):
                 del os.environ[k]
             else:
                 os.environ[k] = v
-    assert M.dugks_kernel_variant(ctx) == VARIANTS[variant or "fused"]
+    if variant is None:
+        assert M.dugks_kernel_variant(ctx) == default_kernel(cfg)
+    else:
+        assert M.dugks_kernel_variant(ctx) == VARIANTS[variant]
     return ctx
 
 
@@ -125,7 +138,7 @@ def case_force(cfg, seed):
     return field(seed, (D,) + shp, 1e-4)
 
 
-@pytest.mark.parametrize("variant", ["fused", "fused-twice", "general"])
+@pytest.mark.parametrize("variant", ["split", "fused", "fused-twice", "general"])
 @pytest.mark.parametrize("cfg", CASES, ids=[c["name"] for c in CASES])
 def test_step_parity_f64(cfg, variant):
     say(f"[parity f64] {cfg['name']} n={cfg['n']} {variant}")
