@@ -193,6 +193,15 @@ void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& me
     P.B7 = (T)(h / (2.0 * tau + h));
     P.C7 = (T)(tau * h / (2.0 * tau + h));
     for (int a = 0; a < 3; ++a) P.G0[a] = (T)(a < D ? c->G[a] : 0.0);
+    {
+        const double cc = std::sqrt(3.0 * c->RT), RT = c->RT, r0 = c->rho0;
+        P.crho = (T)(cc / r0);
+        P.invRT = (T)(1.0 / RT);
+        P.eqH = (T)(r0 / (2.0 * RT));
+        P.eqB = (T)(r0 * cc / RT);
+        P.eqC = (T)(r0 * cc * cc / (2.0 * RT * RT));
+        P.sG = (T)(cc / RT);
+    }
     for (int s = 0; s < 6; ++s) {
         for (int a = 0; a < 3; ++a) P.uw[s][a] = (T)(a < D ? c->uw[s][a] : 0.0);
         P.rhow[s] = (T)(c->rho0 + c->pw[s] / c->RT);

@@ -51,6 +51,10 @@ struct Inst {
     T B1, C1;      // Eq. (f_bar_+) in deviation form: phi = f + B1 (feq - f) + C1 S
     T B7, C7;      // step 7:  f = fbar + B7 (feq - fbar) + C7 S
     T G0[3];
+    // point-formula constants (host-computed): c / rho0, 1 / RT and the
+    // factored Eqs. (icfeq), (S): eqH = rho0 / (2 RT), eqB = rho0 c / RT,
+    // eqC = rho0 c^2 / (2 RT^2), sG = c / RT
+    T crho, invRT, eqH, eqB, eqC, sG;
     T uw[6][3];
     T rhow[6];     // rho0 + p_w / RT (pressure condition)
     T rlo[3], rhi[3]; // ghost(-1) = (1-rlo) phi(0) + rlo phi(1); ghost(n) likewise
@@ -96,6 +100,66 @@ __device__ __forceinline__ T src_fac(int q, const T* u, const T* G, T c, T invRT
         s += G[a] * ((e == 0 ? T(0) : (e > 0 ? c : -c)) - u[a]);
     }
     return s * invRT;
+}
+
+// Eqs. (icfeq) and (S) at one point, factored for evaluation over many
+// velocities: with eu = e_q . u,
+//   feq_q = W_q (a + eu (eqB + eqC eu)),   a = rho - eqH |u|^2,
+//   S_q   = (sG e_q . G - g) feq_q,         g = G . u / RT,
+// i.e. Eq. (icfeq) with xi = c e expanded in powers of e.u, and Eq. (S)
+// with xi . G = c e . G.  Per point: a, g and the vectors; per velocity a
+// few fused multiply-adds.
+template <typename T>
+struct EqPt {
+    T a, g;
+    T u[3], G[3];
+};
+
+template <class LAT, typename T>
+__device__ __forceinline__ EqPt<T> eq_point(const Inst<T>& P, T rho, const T* u, const T* G)
+{
+    EqPt<T> E;
+    T uu = T(0), gu = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        E.u[a] = a < LAT::D ? u[a] : T(0);
+        E.G[a] = (a < LAT::D && G) ? G[a] : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < LAT::D; ++a) {
+        uu += E.u[a] * E.u[a];
+        gu += E.G[a] * E.u[a];
+    }
+    E.a = rho - P.eqH * uu;
+    E.g = gu * P.invRT;
+    return E;
+}
+
+// e_q . v for a compile-time velocity q
+template <class LAT, typename T>
+__device__ __forceinline__ T e_dot(int q, const T* v)
+{
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < LAT::D; ++a) {
+        if (LAT::e(q, a) == 1) s += v[a];
+        if (LAT::e(q, a) == -1) s -= v[a];
+    }
+    return s;
+}
+
+template <class LAT, typename T>
+__device__ __forceinline__ T feq_pt(const Inst<T>& P, const EqPt<T>& E, int q)
+{
+    const T eu = e_dot<LAT, T>(q, E.u);
+    return T(LAT::w(q)) * (E.a + eu * (P.eqB + P.eqC * eu));
+}
+
+// S_q / feq_q
+template <class LAT, typename T>
+__device__ __forceinline__ T srcf_pt(const Inst<T>& P, const EqPt<T>& E, int q)
+{
+    return e_dot<LAT, T>(q, E.G) * P.sG - E.g;
 }
 
 template <class LAT, typename T>

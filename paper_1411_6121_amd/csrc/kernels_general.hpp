@@ -38,7 +38,6 @@ __device__ __forceinline__ void phi_from(const Inst<T>& P, const T (&fv)[LAT::Q]
                                          T gt, T* out)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    const T invRT = T(1) / P.RT;
     T rho = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -49,16 +48,17 @@ __device__ __forceinline__ void phi_from(const Inst<T>& P, const T (&fv)[LAT::Q]
             if (LAT::e(q, a) == -1) j[a] -= fv[q];
         }
     }
-    T G[3], u[3];
+    T G[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
-        u[a] = P.c * j[a] / P.rho0 + P.h * G[a];
+        u[a] = P.crho * j[a] + P.h * G[a];
     }
+    const EqPt<T> E = eq_point<LAT, T>(P, rho, u, G);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T fe = feq_q<LAT, T>(q, rho, u, P.rho0, P.c, invRT);
-        const T S = src_fac<LAT, T>(q, u, G, P.c, invRT) * fe;
+        const T fe = feq_pt<LAT, T>(P, E, q);
+        const T S = srcf_pt<LAT, T>(P, E, q) * fe;
         out[q] = fv[q] + P.B1 * (fe - fv[q]) + P.C1 * S;
     }
 }
@@ -204,75 +204,6 @@ __device__ __forceinline__ CellMetric<T> load_metric(const Inst<T>& P, int a, in
     return CellMetric<T>{m.w[i], m.w[i + 1], m.gn[i], m.gn[i + 1], m.cp[i], m.c0[i], m.cm[i], m.fdx[i]};
 }
 
-template <typename T>
-__device__ __forceinline__ T pick1(T x, T y, T z, int a) { return a == 0 ? x : (a == 1 ? y : z); }
-
-template <typename T>
-__device__ __forceinline__ CellMetric<T> pick(const CellMetric<T> x, const CellMetric<T> y, const CellMetric<T> z,
-                                              int a)
-{
-    // register selects on values (never through an indexed array)
-    CellMetric<T> r;
-    r.wl = pick1(x.wl, y.wl, z.wl, a);
-    r.wu = pick1(x.wu, y.wu, z.wu, a);
-    r.gl = pick1(x.gl, y.gl, z.gl, a);
-    r.gu = pick1(x.gu, y.gu, z.gu, a);
-    r.cp = pick1(x.cp, y.cp, z.cp, a);
-    r.c0 = pick1(x.c0, y.c0, z.c0, a);
-    r.cm = pick1(x.cm, y.cm, z.cm, a);
-    r.fdx = pick1(x.fdx, y.fdx, z.fdx, a);
-    return r;
-}
-
-// e_{q,a} for a run-time axis a (q compile-time): a select of constants
-template <class LAT>
-__device__ __forceinline__ int e_rt(int q, int a)
-{
-    return a == 0 ? LAT::e(q, 0) : (a == 1 ? LAT::e(q, 1) : LAT::e(q, 2));
-}
-
-// Appendix steps 3-4 on the lower (upper = false) or upper face of the cell
-// along axis a: the face value of f-bar-plus (linear in the normal
-// direction) minus h xi . grad, with the normal gradient from the two cells
-// and each tangential gradient from the two cells' cell-centred derivatives
-// (= bilinear cross-point difference over the face width).
-template <class LAT, typename T, class ACC>
-__device__ __forceinline__ void recon_face(const Inst<T>& P, const ACC& ph, int a, bool upper,
-                                           const CellMetric<T>& ma, const CellMetric<T>& m1, int t1,
-                                           const CellMetric<T>& m2, int t2, T* out)
-{
-    constexpr int Q = LAT::Q, D = LAT::D;
-    const int lo = upper ? 0 : -1;  // offset of the left cell along a
-    const auto bL = ph.base(a == 0 ? lo : 0, a == 1 ? lo : 0, a == 2 ? lo : 0);
-    const auto bR = ph.base(a == 0 ? lo + 1 : 0, a == 1 ? lo + 1 : 0, a == 2 ? lo + 1 : 0);
-    const auto u1 = ph.up(t1), d1 = ph.dn(t1);
-    const auto u2 = ph.up(t2), d2 = ph.dn(t2);
-    const T w = upper ? ma.wu : ma.wl;
-    const T hcg = P.h * P.c * (upper ? ma.gu : ma.gl);
-    const T hc = P.h * P.c;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const T pL = ph.get(q, bL), pR = ph.get(q, bR);
-        const int ea = e_rt<LAT>(q, a);
-        T v = pL + w * (pR - pL) - T(ea) * hcg * (pR - pL);
-        const int e1 = e_rt<LAT>(q, t1);
-        if (e1 != 0) {
-            const T dL = m1.cp * ph.get(q, bL + u1) + m1.c0 * pL + m1.cm * ph.get(q, bL - d1);
-            const T dR = m1.cp * ph.get(q, bR + u1) + m1.c0 * pR + m1.cm * ph.get(q, bR - d1);
-            v -= T(e1) * hc * (dL + w * (dR - dL));
-        }
-        if (D == 3) {
-            const int e2 = e_rt<LAT>(q, t2);
-            if (e2 != 0) {
-                const T dL = m2.cp * ph.get(q, bL + u2) + m2.c0 * pL + m2.cm * ph.get(q, bL - d2);
-                const T dR = m2.cp * ph.get(q, bR + u2) + m2.c0 * pR + m2.cm * ph.get(q, bR - d2);
-                v -= T(e2) * hc * (dL + w * (dR - dL));
-            }
-        }
-        out[q] = v;
-    }
-}
-
 // interface moments (Appendix step 6): rho, u = j/rho0 + h/2 G
 template <class LAT, typename T>
 __device__ __forceinline__ void face_moments(const Inst<T>& P, const T* fb, const T* G, T& rho, T* u)
@@ -289,7 +220,9 @@ __device__ __forceinline__ void face_moments(const Inst<T>& P, const T* fb, cons
         }
     }
 #pragma unroll
-    for (int a = 0; a < LAT::D; ++a) u[a] = P.c * j[a] / P.rho0 + T(0.5) * P.h * G[a];
+    for (int a = 0; a < LAT::D; ++a) u[a] = P.crho * j[a] + T(0.5) * P.h * G[a];
+#pragma unroll
+    for (int a = LAT::D; a < 3; ++a) u[a] = T(0);
 }
 
 // What the NEQ rule needs from the opposite interface x_c of a wall cell:
@@ -305,12 +238,12 @@ template <class LAT, typename T>
 __device__ __forceinline__ void neq_capture(const Inst<T>& P, int a, const T* oppf, const T* Gopp,
                                             NeqInfo<LAT, T>& I)
 {
-    const T invRT = T(1) / P.RT;
     face_moments<LAT, T>(P, oppf, Gopp, I.rc, I.uc);
+    const EqPt<T> E = eq_point<LAT, T>(P, I.rc, I.uc, nullptr);
 #pragma unroll
     for (int q = 0; q < LAT::Q; ++q) {
         if (LAT::e(q, a) == 0) continue;
-        I.neq[q] = oppf[q] - feq_q<LAT, T>(q, I.rc, I.uc, P.rho0, P.c, invRT);
+        I.neq[q] = oppf[q] - feq_pt<LAT, T>(P, E, q);
     }
 }
 
@@ -322,7 +255,6 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
     constexpr int Q = LAT::Q, D = LAT::D;
     const int a = s >> 1;
     const int sg = (s & 1) ? 1 : -1;  // outward normal = sg e_a
-    const T invRT = T(1) / P.RT;
     const int kind = P.bc[s];
     if (kind == BC_BOUNCE_BACK) {
 #pragma unroll
@@ -331,7 +263,7 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
             T xu = T(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) xu += xi_of<LAT, T>(q, d, P.c) * P.uw[s][d];
-            wall[q] = wall[LAT::opp(q)] + T(2) * P.rho0 * T(LAT::w(q)) * xu * invRT;
+            wall[q] = wall[LAT::opp(q)] + T(2) * P.rho0 * T(LAT::w(q)) * xu * P.invRT;
         }
         return;
     }
@@ -345,10 +277,11 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = I.uc[d];
     }
+    const EqPt<T> E = eq_point<LAT, T>(P, ra, ua, nullptr);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (LAT::e(q, a) * sg >= 0) continue;
-        wall[q] = feq_q<LAT, T>(q, ra, ua, P.rho0, P.c, invRT) + I.neq[q];
+        wall[q] = feq_pt<LAT, T>(P, E, q) + I.neq[q];
     }
 }
 
@@ -356,91 +289,14 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
 template <class LAT, typename T>
 __device__ __forceinline__ void face_original(const Inst<T>& P, int a, T* fb, const T* G)
 {
-    const T invRT = T(1) / P.RT;
     T rho, u[3];
     face_moments<LAT, T>(P, fb, G, rho, u);
+    const EqPt<T> E = eq_point<LAT, T>(P, rho, u, G);
 #pragma unroll
     for (int q = 0; q < LAT::Q; ++q) {
         if (LAT::e(q, a) == 0) continue;
-        const T fe = feq_q<LAT, T>(q, rho, u, P.rho0, P.c, invRT);
-        const T S = src_fac<LAT, T>(q, u, G, P.c, invRT) * fe;
-        fb[q] = fb[q] + P.B7 * (fe - fb[q]) + P.C7 * S;
-    }
-}
-
-template <class LAT, typename T>
-__device__ __forceinline__ void neq_capture_rt(const Inst<T>& P, int a, const T* oppf, const T* Gopp,
-                                               NeqInfo<LAT, T>& I)
-{
-    const T invRT = T(1) / P.RT;
-    face_moments<LAT, T>(P, oppf, Gopp, I.rc, I.uc);
-#pragma unroll
-    for (int q = 0; q < LAT::Q; ++q) I.neq[q] = oppf[q] - feq_q<LAT, T>(q, I.rc, I.uc, P.rho0, P.c, invRT);
-}
-
-template <class LAT, typename T>
-__device__ __forceinline__ void wall_rule_rt(const Inst<T>& P, int s, int a, T* wall, const NeqInfo<LAT, T>& I)
-{
-    constexpr int Q = LAT::Q, D = LAT::D;
-    const int sg = (s & 1) ? 1 : -1;  // outward normal = sg e_a
-    const T invRT = T(1) / P.RT;
-    int kind = P.bc[0];
-#pragma unroll
-    for (int k = 1; k < 6; ++k)
-        if (k == s) kind = P.bc[k];
-    T uws[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) uws[d] = P.uw[0][d];
-#pragma unroll
-    for (int k = 1; k < 6; ++k)
-        if (k == s)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) uws[d] = P.uw[k][d];
-    if (kind == BC_BOUNCE_BACK) {
-        T pre[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) pre[q] = wall[q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (e_rt<LAT>(q, a) * sg >= 0) continue;
-            T xu = T(0);
-#pragma unroll
-            for (int d = 0; d < D; ++d) xu += xi_of<LAT, T>(q, d, P.c) * uws[d];
-            wall[q] = pre[LAT::opp(q)] + T(2) * P.rho0 * T(LAT::w(q)) * xu * invRT;
-        }
-        return;
-    }
-    T ra, ua[3];
-    if (kind == BC_NEQ_VELOCITY) {
-        ra = I.rc;
-#pragma unroll
-        for (int d = 0; d < D; ++d) ua[d] = uws[d];
-    } else {
-        ra = P.rho0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            if (k == s) ra = P.rhow[k];
-#pragma unroll
-        for (int d = 0; d < D; ++d) ua[d] = I.uc[d];
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (e_rt<LAT>(q, a) * sg >= 0) continue;
-        wall[q] = feq_q<LAT, T>(q, ra, ua, P.rho0, P.c, invRT) + I.neq[q];
-    }
-}
-
-template <class LAT, typename T>
-__device__ __forceinline__ void face_original_rt(const Inst<T>& P, int a, T* fb, const T* G)
-{
-    const T invRT = T(1) / P.RT;
-    T rho, u[3];
-    face_moments<LAT, T>(P, fb, G, rho, u);
-#pragma unroll
-    for (int q = 0; q < LAT::Q; ++q) {
-        if (e_rt<LAT>(q, a) == 0) continue;
-        const T fe = feq_q<LAT, T>(q, rho, u, P.rho0, P.c, invRT);
-        const T S = src_fac<LAT, T>(q, u, G, P.c, invRT) * fe;
+        const T fe = feq_pt<LAT, T>(P, E, q);
+        const T S = srcf_pt<LAT, T>(P, E, q) * fe;
         fb[q] = fb[q] + P.B7 * (fe - fb[q]) + P.C7 * S;
     }
 }

@@ -84,7 +84,6 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
                                          bool has_field, T gt, T sg, T (&out)[LAT::REST], T& orest)
 {
     constexpr int K = LAT::REST, D = LAT::D;
-    const T invRT = T(1) / P.RT;
     T rh = T(0), sj[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -102,18 +101,19 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
         const T jh = sg * sj[a];
         const T j = jh + partner(jh);
         G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
-        u[a] = P.c * j / P.rho0 + P.h * G[a];
+        u[a] = P.crho * j + P.h * G[a];
         us[a] = sg * u[a];
         Gs[a] = sg * G[a];
     }
+    const EqPt<T> E = eq_point<LAT, T>(P, rho, us, Gs);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const T fe = feq_q<LAT, T>(k, rho, us, P.rho0, P.c, invRT);
-        const T S = src_fac<LAT, T>(k, us, Gs, P.c, invRT) * fe;
+        const T fe = feq_pt<LAT, T>(P, E, k);
+        const T S = srcf_pt<LAT, T>(P, E, k) * fe;
         out[k] = fv[k] + P.B1 * (fe - fv[k]) + P.C1 * S;
     }
-    const T fe = feq_q<LAT, T>(LAT::REST, rho, u, P.rho0, P.c, invRT);
-    const T S = src_fac<LAT, T>(LAT::REST, u, G, P.c, invRT) * fe;
+    const T fe = feq_pt<LAT, T>(P, E, LAT::REST);
+    const T S = srcf_pt<LAT, T>(P, E, LAT::REST) * fe;
     orest = fr + P.B1 * (fe - fr) + P.C1 * S;
 }
 
@@ -170,8 +170,10 @@ __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const T jh = sg * sj[a];
-        u[a] = P.c * (jh + partner(jh)) / P.rho0 + T(0.5) * P.h * G[a];
+        u[a] = P.crho * (jh + partner(jh)) + T(0.5) * P.h * G[a];
     }
+#pragma unroll
+    for (int a = D; a < 3; ++a) u[a] = T(0);
 }
 
 // what the NEQ rule needs from the opposite interface of a wall cell
@@ -185,15 +187,15 @@ template <class LAT, typename T, int A>
 __device__ __forceinline__ void neq_capture_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
                                                  NeqHalf<LAT, T>& I)
 {
-    const T invRT = T(1) / P.RT;
     moments_half<LAT, T>(P, fb, fr, G, sg, I.rc, I.uc);
     T us[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < LAT::D; ++a) us[a] = sg * I.uc[a];
+    const EqPt<T> E = eq_point<LAT, T>(P, I.rc, us, nullptr);
 #pragma unroll
     for (int k = 0; k < LAT::REST; ++k) {
         if (LAT::e(k, A) == 0) continue;
-        I.neq[k] = fb[k] - feq_q<LAT, T>(k, I.rc, us, P.rho0, P.c, invRT);
+        I.neq[k] = fb[k] - feq_pt<LAT, T>(P, E, k);
     }
 }
 
@@ -204,7 +206,6 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
                                           const NeqHalf<LAT, T>& I, T sg, int sgi)
 {
     constexpr int K = LAT::REST, D = LAT::D;
-    const T invRT = T(1) / P.RT;
     const int kind = P.bc[s];
     if (kind == BC_BOUNCE_BACK) {
         T other[K];
@@ -218,7 +219,7 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
             T xu = T(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) xu += xi_of<LAT, T>(k, d, P.c) * P.uw[s][d];
-            wall[k] = other[k] + T(2) * P.rho0 * T(LAT::w(k)) * (sg * xu) * invRT;
+            wall[k] = other[k] + T(2) * P.rho0 * T(LAT::w(k)) * (sg * xu) * P.invRT;
         }
         return;
     }
@@ -232,11 +233,12 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = sg * I.uc[d];
     }
+    const EqPt<T> E = eq_point<LAT, T>(P, ra, ua, nullptr);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (LAT::e(k, A) == 0) continue;
         if (sgi * LAT::e(k, A) * sgs >= 0) continue;
-        wall[k] = feq_q<LAT, T>(k, ra, ua, P.rho0, P.c, invRT) + I.neq[k];
+        wall[k] = feq_pt<LAT, T>(P, E, k) + I.neq[k];
     }
 }
 
@@ -253,7 +255,6 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
     const int n = P.n[A];
     const bool wall_lo = !P.per[A] && f == 0;
     const bool wall_hi = !P.per[A] && f == n;
-    const T invRT = T(1) / P.RT;
     NeqHalf<LAT, T> info;
     asm volatile("" ::: "memory");
     T fb[K], fr, G[3];
@@ -278,11 +279,12 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
         us[a] = sg * u[a];
         Gs[a] = sg * G[a];
     }
+    const EqPt<T> E = eq_point<LAT, T>(P, rho, us, Gs);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (LAT::e(k, A) == 0) continue;
-        const T fe = feq_q<LAT, T>(k, rho, us, P.rho0, P.c, invRT);
-        const T S = src_fac<LAT, T>(k, us, Gs, P.c, invRT) * fe;
+        const T fe = feq_pt<LAT, T>(P, E, k);
+        const T S = srcf_pt<LAT, T>(P, E, k) * fe;
         out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]) + P.C7 * S;  // step 7
     }
 }
