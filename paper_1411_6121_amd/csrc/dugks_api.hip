@@ -202,6 +202,14 @@ void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& me
         P.eqC = (T)(r0 * cc * cc / (2.0 * RT * RT));
         P.sG = (T)(cc / RT);
     }
+    P.uni = 1;
+    for (int a = 0; a < D; ++a) {
+        if (c->mesh[a] != DUGKS_UNIFORM) P.uni = 0;
+        const double dx = c->L[a] / c->n[a];
+        P.ugn[a] = (T)(1.0 / dx);
+        P.uct[a] = (T)(0.25 / dx);
+        P.ufdx[a] = (T)(dt / dx);
+    }
     for (int s = 0; s < 6; ++s) {
         for (int a = 0; a < 3; ++a) P.uw[s][a] = (T)(a < D ? c->uw[s][a] : 0.0);
         P.rhow[s] = (T)(c->rho0 + c->pw[s] / c->RT);

@@ -55,6 +55,13 @@ struct Inst {
     // factored Eqs. (icfeq), (S): eqH = rho0 / (2 RT), eqB = rho0 c / RT,
     // eqC = rho0 c^2 / (2 RT^2), sG = c / RT
     T crho, invRT, eqH, eqB, eqC, sG;
+    // uniform mesh (every active axis): uni = 1 and per axis, with
+    // Delta = L / N, the face weight is 1/2 and the derivative coefficients
+    // are ugn = 1 / Delta (normal difference), uct = 1 / (4 Delta) (the face's
+    // tangential derivative times 1/2 per neighbour difference) and
+    // ufdx = dt / Delta (flux scale)
+    int uni;
+    T ugn[3], uct[3], ufdx[3];
     T uw[6][3];
     T rhow[6];     // rho0 + p_w / RT (pressure condition)
     T rlo[3], rhi[3]; // ghost(-1) = (1-rlo) phi(0) + rlo phi(1); ghost(n) likewise

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restric
 // registers for the next plane); after a barrier every updating cell takes
 // the differences of its two faces per axis (steps 8-9).
 // ---------------------------------------------------------------------------
-template <class LAT, typename T, int BX, int BY, bool PF>
+template <class LAT, typename T, int BX, int BY, bool PF, bool UNI>
 __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                             T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                             int ck, T* lds)
@@ -377,8 +377,8 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
         ci[2] = (D == 3) ? p0 : 0;
         const CellMetric<T> cmm = load_metric(P, M, p0);
         const auto ph = phi_view(p0);
-        if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, zlo);
-        else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, zlo);
+        if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, zlo);
+        else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, zlo);
     }
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
@@ -412,22 +412,22 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
         T zhi[NM];
         if (xface) {
             T v[NX];
-            if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, v);
-            else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, v);
+            if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 0, UNI>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, v);
+            else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 0, UNI>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, v);
 #pragma unroll
             for (int k = 0; k < NX; ++k) fxb[(k * BY + ty) * BX + tx] = v[k];
         }
         if constexpr (D == 3) {
             if (yface) {
                 T v[NY];
-                face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 1>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, v);
+                face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, 1, UNI>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, v);
 #pragma unroll
                 for (int k = 0; k < NY; ++k) fyb[(k * BY + ty) * BX + tx] = v[k];
             }
         }
         if (upd_col) {
-            if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, zhi);
-            else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, zhi);
+            if constexpr (D == 3) face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, zhi);
+            else face_once<LAT, T, LdsPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, zhi);
         }
         __syncthreads();
         if (upd_col) {
@@ -439,7 +439,7 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
                 const T p = ph.get(q, ph.cur);
                 acc[q] = p + (p - fz[q]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
             }
-            const T sx = cmx.fdx * P.c, sm = cmm.fdx * P.c;
+            const T sx = (UNI ? P.ufdx[0] : cmx.fdx) * P.c, sm = (UNI ? P.ufdx[M] : cmm.fdx) * P.c;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if (LAT::e(q, 0) != 0) {
@@ -451,7 +451,7 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
                     if (LAT::e(q, 1) != 0) {
                         const int k = cross_slot<LAT, 1>(q);
                         const T d = fyb[(k * BY + ty) * BX + tx] - fyb[(k * BY + ty - 1) * BX + tx];
-                        acc[q] -= T(LAT::e(q, 1)) * (cmy.fdx * P.c) * d;
+                        acc[q] -= T(LAT::e(q, 1)) * ((UNI ? P.ufdx[1] : cmy.fdx) * P.c) * d;
                     }
                 }
                 if (LAT::e(q, M) != 0) {
@@ -469,7 +469,7 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
 
 // FF: the launch carries a force field (without one the kernel is compiled
 // with a null field and no field code)
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI>
 __global__ DUGKS_KERNEL_BOUNDS(BX * BY, MINW, (max_waves_per_eu<LAT, T, false>())) void k_fused2(const Inst<T>* __restrict__ Pp, const T* __restrict__ fin,
                                                           const T* __restrict__ force, T* __restrict__ fout,
                                                           double t, int chunk, int tiles0, int tiles)
@@ -479,7 +479,7 @@ __global__ DUGKS_KERNEL_BOUNDS(BX * BY, MINW, (max_waves_per_eu<LAT, T, false>()
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int ntile = (int)tiles;
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    fused2_body<LAT, T, BX, BY, PF>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % ntile, b / ntile,
+    fused2_body<LAT, T, BX, BY, PF, UNI>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % ntile, b / ntile,
                                 reinterpret_cast<T*>(smem_raw));
 }
 
@@ -511,8 +511,13 @@ __global__ DUGKS_KERNEL_BOUNDS(BX * BY, MINW, (max_waves_per_eu<LAT, T, false>()
     const double t = (double)(*step0 + step) * P.dtd;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const T* force = (FF && forces && P.foff >= 0) ? forces + P.foff : nullptr;
-    fused2_body<LAT, T, BX, BY, PF>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
-                                    local / ntile, reinterpret_cast<T*>(smem_raw));
+    // per instance: the uniform-mesh body where every axis is uniform
+    if (P.uni)
+        fused2_body<LAT, T, BX, BY, PF, true>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0,
+                                              local % ntile, local / ntile, reinterpret_cast<T*>(smem_raw));
+    else
+        fused2_body<LAT, T, BX, BY, PF, false>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0,
+                                               local % ntile, local / ntile, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -560,7 +565,7 @@ static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     return hip_check(ctx, hipGetLastError(), "fused step launch");
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI>
 static int launch_fused2_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force,
                             double t, hipStream_t st, int chunk)
 {
@@ -569,7 +574,7 @@ static int launch_fused2_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, v
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
     const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = fused2_lds<LAT, T, BX, BY>();
-    auto kern = k_fused2<LAT, T, BX, BY, MINW, PF, FF>;
+    auto kern = k_fused2<LAT, T, BX, BY, MINW, PF, FF, UNI>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -587,8 +592,12 @@ template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
 static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
                          hipStream_t st, int chunk)
 {
-    if (force) return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, true>(ctx, P, fin, fout, force, t, st, chunk);
-    return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, false>(ctx, P, fin, fout, force, t, st, chunk);
+    if (P.uni) {
+        if (force) return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, true, true>(ctx, P, fin, fout, force, t, st, chunk);
+        return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+    }
+    if (force) return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, true, false>(ctx, P, fin, fout, force, t, st, chunk);
+    return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, false, false>(ctx, P, fin, fout, force, t, st, chunk);
 }
 
 // tile shapes: D3Q19 18x14 columns (16x12 interior), D2Q9 rows of 128

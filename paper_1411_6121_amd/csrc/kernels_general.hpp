@@ -387,7 +387,7 @@ __host__ __device__ constexpr int cross_count()
     return cross_slot<LAT, A>(LAT::Q);
 }
 
-template <class LAT, typename T, class ACC, int A>
+template <class LAT, typename T, class ACC, int A, bool UNI>
 __device__ __forceinline__ void recon_at(const Inst<T>& P, const ACC& ph, int off, T w, T gn, const CellMetric<T>& mx,
                                          const CellMetric<T>& my, const CellMetric<T>& mz, T* out)
 {
@@ -399,15 +399,24 @@ __device__ __forceinline__ void recon_at(const Inst<T>& P, const ACC& ph, int of
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const T pL = ph.get(q, bL), pR = ph.get(q, bR);
-        T v = pL + w * (pR - pL) - T(LAT::e(q, A)) * hcg * (pR - pL);
+        T v;
+        if constexpr (UNI) v = T(0.5) * (pL + pR);
+        else v = pL + w * (pR - pL);
+        if (LAT::e(q, A) != 0) v -= T(LAT::e(q, A)) * hcg * (pR - pL);
 #pragma unroll
         for (int t = 0; t < D; ++t) {
             if (t == A || LAT::e(q, t) == 0) continue;
-            const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
             const auto u = ph.up(t), d = ph.dn(t);
-            const T dL = mt.cp * ph.get(q, bL + u) + mt.c0 * pL + mt.cm * ph.get(q, bL - d);
-            const T dR = mt.cp * ph.get(q, bR + u) + mt.c0 * pR + mt.cm * ph.get(q, bR - d);
-            v -= T(LAT::e(q, t)) * hc * (dL + w * (dR - dL));
+            if constexpr (UNI) {
+                // uniform mesh: (1/2)(d(L) + d(R)), d = (phi(+t) - phi(-t)) / (2 Delta)
+                const T s = (ph.get(q, bL + u) - ph.get(q, bL - d)) + (ph.get(q, bR + u) - ph.get(q, bR - d));
+                v -= T(LAT::e(q, t)) * (hc * P.uct[t]) * s;
+            } else {
+                const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
+                const T dL = mt.cp * ph.get(q, bL + u) + mt.c0 * pL + mt.cm * ph.get(q, bL - d);
+                const T dR = mt.cp * ph.get(q, bR + u) + mt.c0 * pR + mt.cm * ph.get(q, bR - d);
+                v -= T(LAT::e(q, t)) * hc * (dL + w * (dR - dL));
+            }
         }
         out[q] = v;
     }
@@ -416,7 +425,7 @@ __device__ __forceinline__ void recon_at(const Inst<T>& P, const ACC& ph, int of
 // ci: global cell coordinates of the thread's cell (tangential ones are
 // used for metrics and force); f: face index along A.  out[cross_slot]
 // receives f_q (step 7) for the velocities crossing the face.
-template <class LAT, typename T, class ACC, int A>
+template <class LAT, typename T, class ACC, int A, bool UNI>
 __device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
                                           int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
                                           const CellMetric<T>& mz, T* out)
@@ -433,13 +442,14 @@ __device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const
         // the opposite interface of the wall cell (its NEQ information)
         const int fo = wall_lo ? 1 : n - 1;
         const int oo = wall_lo ? off + 1 : off - 1;
-        recon_at<LAT, T, ACC, A>(P, ph, oo, m.w[fo], m.gn[fo], mx, my, mz, fb);
-        face_force<LAT, T>(P, force, A, fo, m.w[fo], ci, gth, G);
+        const T wo = UNI ? T(0.5) : m.w[fo];
+        recon_at<LAT, T, ACC, A, UNI>(P, ph, oo, wo, UNI ? P.ugn[A] : m.gn[fo], mx, my, mz, fb);
+        face_force<LAT, T>(P, force, A, fo, wo, ci, gth, G);
         neq_capture<LAT, T>(P, A, fb, G, info);
         asm volatile("" ::: "memory");
     }
-    const T w = m.w[f];
-    recon_at<LAT, T, ACC, A>(P, ph, off, w, m.gn[f], mx, my, mz, fb);
+    const T w = UNI ? T(0.5) : m.w[f];
+    recon_at<LAT, T, ACC, A, UNI>(P, ph, off, w, UNI ? P.ugn[A] : m.gn[f], mx, my, mz, fb);
     face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
     if (wall_lo) wall_rule<LAT, T>(P, 2 * A, fb, info);
     if (wall_hi) wall_rule<LAT, T>(P, 2 * A + 1, fb, info);

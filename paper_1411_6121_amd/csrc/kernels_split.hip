@@ -120,7 +120,7 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
 // Appendix steps 3-4 for the lane's velocities on the interface of axis A
 // between the cells at offsets off and off+1 (weight w of the right cell,
 // normal-difference scale gn); the rest velocity (no gradient term) too
-template <class LAT, typename T, class ACC, int A>
+template <class LAT, typename T, class ACC, int A, bool UNI>
 __device__ __forceinline__ void recon_half(const Inst<T>& P, const ACC& ph, int off, T w, T gn,
                                            const CellMetric<T>& mx, const CellMetric<T>& my,
                                            const CellMetric<T>& mz, T sg, T (&out)[LAT::REST], T& orest)
@@ -133,21 +133,30 @@ __device__ __forceinline__ void recon_half(const Inst<T>& P, const ACC& ph, int 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const T pL = ph.get(k, bL), pR = ph.get(k, bR);
-        T v = pL + w * (pR - pL);
+        T v;
+        if constexpr (UNI) v = T(0.5) * (pL + pR);
+        else v = pL + w * (pR - pL);
         if (LAT::e(k, A) != 0) v -= T(LAT::e(k, A)) * hcg * (pR - pL);
 #pragma unroll
         for (int t = 0; t < D; ++t) {
             if (t == A || LAT::e(k, t) == 0) continue;
-            const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
             const int u = ph.up(t), d = ph.dn(t);
-            const T dL = mt.cp * ph.get(k, bL + u) + mt.c0 * pL + mt.cm * ph.get(k, bL - d);
-            const T dR = mt.cp * ph.get(k, bR + u) + mt.c0 * pR + mt.cm * ph.get(k, bR - d);
-            v -= T(LAT::e(k, t)) * hc * (dL + w * (dR - dL));
+            if constexpr (UNI) {
+                // uniform mesh: (1/2)(d(L) + d(R)), d = (phi(+t) - phi(-t)) / (2 Delta)
+                const T s2 = (ph.get(k, bL + u) - ph.get(k, bL - d)) + (ph.get(k, bR + u) - ph.get(k, bR - d));
+                v -= T(LAT::e(k, t)) * (hc * P.uct[t]) * s2;
+            } else {
+                const CellMetric<T>& mt = t == 0 ? mx : (t == 1 ? my : mz);
+                const T dL = mt.cp * ph.get(k, bL + u) + mt.c0 * pL + mt.cm * ph.get(k, bL - d);
+                const T dR = mt.cp * ph.get(k, bR + u) + mt.c0 * pR + mt.cm * ph.get(k, bR - d);
+                v -= T(LAT::e(k, t)) * hc * (dL + w * (dR - dL));
+            }
         }
         out[k] = v;
     }
     const T rL = ph.rest(bL), rR = ph.rest(bR);
-    orest = rL + w * (rR - rL);
+    if constexpr (UNI) orest = T(0.5) * (rL + rR);
+    else orest = rL + w * (rR - rL);
 }
 
 // interface moments (Appendix step 6) from the two lanes' values
@@ -245,7 +254,7 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
 // The interface of axis A with index f between the cells at offsets off and
 // off+1: steps 3-7 for the lane's velocities; out[half_cross_slot] receives
 // f (step 7) of the lane's velocities crossing the face.
-template <class LAT, typename T, class ACC, int A>
+template <class LAT, typename T, class ACC, int A, bool UNI>
 __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
                                           int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
                                           const CellMetric<T>& mz, T sg, int sgi, T* out)
@@ -261,13 +270,14 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
     if (wall_lo || wall_hi) {
         const int fo = wall_lo ? 1 : n - 1;
         const int oo = wall_lo ? off + 1 : off - 1;
-        recon_half<LAT, T, ACC, A>(P, ph, oo, m.w[fo], m.gn[fo], mx, my, mz, sg, fb, fr);
-        face_force<LAT, T>(P, force, A, fo, m.w[fo], ci, gth, G);
+        const T wo = UNI ? T(0.5) : m.w[fo];
+        recon_half<LAT, T, ACC, A, UNI>(P, ph, oo, wo, UNI ? P.ugn[A] : m.gn[fo], mx, my, mz, sg, fb, fr);
+        face_force<LAT, T>(P, force, A, fo, wo, ci, gth, G);
         neq_capture_half<LAT, T, A>(P, fb, fr, G, sg, info);
         asm volatile("" ::: "memory");
     }
-    const T w = m.w[f];
-    recon_half<LAT, T, ACC, A>(P, ph, off, w, m.gn[f], mx, my, mz, sg, fb, fr);
+    const T w = UNI ? T(0.5) : m.w[f];
+    recon_half<LAT, T, ACC, A, UNI>(P, ph, off, w, UNI ? P.ugn[A] : m.gn[f], mx, my, mz, sg, fb, fr);
     face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
     if (wall_lo) wall_half<LAT, T, A>(P, 2 * A, -1, fb, info, sg, sgi);
     if (wall_hi) wall_half<LAT, T, A>(P, 2 * A + 1, 1, fb, info, sg, sgi);
@@ -298,7 +308,7 @@ __host__ __device__ constexpr int split_threads()
 
 // One workgroup's work: tile `tile` (of tiles0 x tiles1) and march chunk
 // `ck` of instance P; fin/fout/force point at the instance's arrays.
-template <class LAT, typename T, int BX, int BY, bool PF>
+template <class LAT, typename T, int BX, int BY, bool PF, bool UNI>
 __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                            T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                            int ck, T* lds)
@@ -466,8 +476,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         ci[2] = (D == 3) ? p0 : 0;
         const CellMetric<T> cmm = load_metric(P, M, p0);
         const auto ph = phi_view(p0);
-        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
-        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
+        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
+        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
     }
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
@@ -502,22 +512,22 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         T zhi[NM > 0 ? NM : 1];
         if (xface) {
             T v[NX];
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
 #pragma unroll
             for (int kc = 0; kc < NX; ++kc) fxb[((h * NX + kc) * BY + ty) * BX + tx] = v[kc];
         }
         if constexpr (D == 3) {
             if (yface) {
                 T v[NY];
-                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
 #pragma unroll
                 for (int kc = 0; kc < NY; ++kc) fyb[((h * NY + kc) * BY + ty) * BX + tx] = v[kc];
             }
         }
         if (upd_col) {
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
         }
         __syncthreads();
         if (upd_col) {
@@ -531,7 +541,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
             }
             const T pr = ph.rest(ph.cur);
             const T accr = pr + (pr - fzr) * T(1.0 / 3.0);
-            const T sx = sg * (cmx.fdx * P.c), sm = sg * (cmm.fdx * P.c);
+            const T sx = sg * ((UNI ? P.ufdx[0] : cmx.fdx) * P.c), sm = sg * ((UNI ? P.ufdx[M] : cmm.fdx) * P.c);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (LAT::e(k, 0) != 0) {
@@ -543,7 +553,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                     if (LAT::e(k, 1) != 0) {
                         const int kc = half_cross_slot<LAT, 1>(k);
                         const T d = fyb[((h * NY + kc) * BY + ty) * BX + tx] - fyb[((h * NY + kc) * BY + ty - 1) * BX + tx];
-                        acc[k] -= T(LAT::e(k, 1)) * (sg * (cmy.fdx * P.c)) * d;
+                        acc[k] -= T(LAT::e(k, 1)) * (sg * ((UNI ? P.ufdx[1] : cmy.fdx) * P.c)) * d;
                     }
                 }
                 if (LAT::e(k, M) != 0) {
@@ -563,7 +573,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
 
 // FF: the launch carries a force field (without one the kernel is compiled
 // with a null field and no field code)
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI>
 __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_eu<LAT, T, true>())) void k_split(const Inst<T>* __restrict__ Pp,
                                                                           const T* __restrict__ fin,
                                                                           const T* __restrict__ force,
@@ -574,7 +584,7 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const Inst<T>& P = *Pp;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    split_body<LAT, T, BX, BY, PF>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % tiles, b / tiles,
+    split_body<LAT, T, BX, BY, PF, UNI>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % tiles, b / tiles,
                                    reinterpret_cast<T*>(smem_raw));
 }
 
@@ -601,8 +611,13 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const double t = (double)(*step0 + step) * P.dtd;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const T* force = (FF && forces && P.foff >= 0) ? forces + P.foff : nullptr;
-    split_body<LAT, T, BX, BY, PF>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile,
-                                   local / ntile, reinterpret_cast<T*>(smem_raw));
+    // per instance: the uniform-mesh body where every axis is uniform
+    if (P.uni)
+        split_body<LAT, T, BX, BY, PF, true>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0,
+                                             local % ntile, local / ntile, reinterpret_cast<T*>(smem_raw));
+    else
+        split_body<LAT, T, BX, BY, PF, false>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0,
+                                              local % ntile, local / ntile, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -615,7 +630,7 @@ static size_t split_lds()
            BX * BY * sizeof(T);
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI>
 static int launch_split_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
                            hipStream_t st, int chunk)
 {
@@ -624,7 +639,7 @@ static int launch_split_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, vo
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
     const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = split_lds<LAT, T, BX, BY>();
-    auto kern = k_split<LAT, T, BX, BY, MINW, PF, FF>;
+    auto kern = k_split<LAT, T, BX, BY, MINW, PF, FF, UNI>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -643,8 +658,12 @@ template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
 static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
                         hipStream_t st, int chunk)
 {
-    if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true>(ctx, P, fin, fout, force, t, st, chunk);
-    return launch_split_ff<LAT, T, BX, BY, MINW, PF, false>(ctx, P, fin, fout, force, t, st, chunk);
+    if (P.uni) {
+        if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true, true>(ctx, P, fin, fout, force, t, st, chunk);
+        return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+    }
+    if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true, false>(ctx, P, fin, fout, force, t, st, chunk);
+    return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, false>(ctx, P, fin, fout, force, t, st, chunk);
 }
 
 int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk)
