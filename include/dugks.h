@@ -190,13 +190,17 @@ int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, doubl
 int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, const void* lam0,
                    void* grad_u, void* grad_force, void* stream);
 
-/* Which step kernel the context uses (diagnostics): 0 = general two-pass
- * kernels, 1 = fused single launch with every interface evaluated by both
- * neighbouring cells, 2 = fused single launch with every interface
- * evaluated once, 3 = as 2 with the velocity set split over two lanes per
- * column.  Default: 3 for D3Q19 FP64 and D2Q9 FP32, 2 otherwise (the
- * faster one on MI355X); the batched step uses the same kernel as the
- * default.  All give the same results to rounding. */
+/* Which step kernel a launch without a force field uses (diagnostics):
+ * 0 = general two-pass kernels, 1 = fused single launch with every
+ * interface evaluated by both neighbouring cells, 2 = fused single launch
+ * with every interface evaluated once, 3 = as 2 with the velocity set split
+ * over two lanes per column.  By default each launch takes the faster one
+ * on MI355X: 3 for D2Q9, for D3Q19 FP64 without a force field and for
+ * D3Q19 FP32 on uniform meshes without one; 2 otherwise.  A batch decides
+ * once for all its instances (uniform meshes, any force field), so batched
+ * and single-instance states are bitwise equal when the instances share
+ * the mesh kind and the presence of a force field.  All kernels give the
+ * same results to rounding. */
 int dugks_kernel_variant(const dugks_ctx* ctx);
 
 /*

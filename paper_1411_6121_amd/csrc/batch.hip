@@ -13,9 +13,9 @@
 #include "kernels_general.hpp"
 
 namespace dugks {
-hipError_t batch_step_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
-                             const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
-                             void* fout, const long long* step0, int step, hipStream_t st);
+hipError_t batch_step_launch(int lattice, int dtype, bool uniform, int variant, const void* insts,
+                             const long long* bstart, const BatchGeom* geom, int n, long long nblocks, const void* fin,
+                             const void* forces, void* fout, const long long* step0, int step, hipStream_t st);
 int fused_tile_variants(int lattice);
 void fused_tile_shape(int lattice, int variant, int* bx, int* by);
 
@@ -50,6 +50,8 @@ using namespace dugks;
 struct dugks_batch {
     int n = 0, lattice = 0, dtype = 0, D = 0, Q = 0, esize = 0;
     int tile = 0, chunk = 0;  // tile-shape variant and march chunk (0 = default) in use
+    bool uniform = true;      // every instance on a uniform mesh
+    bool any_field = false;   // some instance has a force field
     std::vector<dugks_config> cfgs;
     std::vector<unsigned char> hinst;  // host images of Inst<T>, n of them
     void* insts_dev = nullptr;
@@ -182,6 +184,9 @@ extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t
     b->Q = b->lattice;
     b->esize = b->dtype == DUGKS_F64 ? 8 : 4;
     b->cfgs.assign(cfgs, cfgs + n);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < b->D; ++a)
+            if (cfgs[i].mesh[a] != DUGKS_UNIFORM) b->uniform = false;
     const int rc = b->dtype == DUGKS_F64 ? build_tables<double>(b, offsets, (hipStream_t)stream)
                                          : build_tables<float>(b, offsets, (hipStream_t)stream);
     if (rc != DUGKS_OK) {
@@ -215,8 +220,10 @@ extern "C" int dugks_batch_init(dugks_batch* b, void* f_out, void* stream)
 
 static int batch_launch_any(dugks_batch* b, const void* fin, void* fout, const void* forces, int step, hipStream_t st)
 {
-    const hipError_t e = batch_step_launch(b->lattice, b->dtype, b->tile, b->insts_dev, b->bstart_dev, b->geom_dev, b->n,
-                                           b->nblocks, fin, forces, fout, b->step_dev, step, st);
+    // without any field the field-free kernels run (as for single instances)
+    const void* fz = b->any_field ? forces : nullptr;
+    const hipError_t e = batch_step_launch(b->lattice, b->dtype, b->uniform, b->tile, b->insts_dev, b->bstart_dev,
+                                           b->geom_dev, b->n, b->nblocks, fin, fz, fout, b->step_dev, step, st);
     return e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EHIP, hipGetErrorString(e));
 }
 
@@ -247,6 +254,9 @@ static int apply_force_offsets(dugks_batch* b, const void* forces, const int64_t
                                        (b->dtype == DUGKS_F64 ? offsetof(Inst<double>, foff) : offsetof(Inst<float>, foff)));
         if (*slot != fo) { *slot = fo; changed = true; }
     }
+    b->any_field = false;
+    for (int i = 0; i < b->n; ++i)
+        if (forces && force_offsets && force_offsets[i] >= 0) b->any_field = true;
     if (changed) {
         drop_graph(b);
         if (hipMemcpy(b->insts_dev, b->hinst.data(), b->hinst.size(), hipMemcpyHostToDevice) != hipSuccess)

@@ -553,7 +553,10 @@ extern "C" int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, d
     return DUGKS_OK;
 }
 
-extern "C" int dugks_kernel_variant(const dugks_ctx* ctx) { return ctx ? ctx->fast : -1; }
+namespace dugks {
+int resolve_step_kernel(const dugks_ctx* ctx, bool field);
+}
+extern "C" int dugks_kernel_variant(const dugks_ctx* ctx) { return ctx ? dugks::resolve_step_kernel(ctx, false) : -1; }
 
 extern "C" void dugks_destroy(dugks_ctx* ctx)
 {

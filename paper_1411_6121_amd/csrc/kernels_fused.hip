@@ -602,7 +602,7 @@ static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void
 
 // tile shapes: D3Q19 18x14 columns (16x12 interior), D2Q9 rows of 128
 // columns (126 interior); chunk = planes marched per workgroup
-static int pick_chunk(const dugks_ctx* ctx)
+static int pick_chunk(const dugks_ctx* ctx, int variant)
 {
     if (ctx->chunk > 0) return std::min(ctx->chunk, std::max(ctx->cfg.n[ctx->D - 1], 1));
     const int D = ctx->D;
@@ -610,21 +610,26 @@ static int pick_chunk(const dugks_ctx* ctx)
     long tiles;
     if (D == 3) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 11) / 12);
     else tiles = (ctx->cfg.n[0] + 125) / 126;
-    // aim for >= 4 workgroups per CU on 256 CUs, but march at least 8 planes
+    // aim for >= 4 workgroups per CU on 256 CUs (the 512-thread FP64 D3Q19
+    // split tiles run one per CU: >= 2.5), but march at least 8 planes
+    const long want = (variant == 3 && D == 3 && ctx->cfg.dtype == DUGKS_F64) ? 640 : 1024;
     int chunk = 16;
-    while (chunk > 8 && tiles * ((nM + chunk - 1) / chunk) < 1024) chunk /= 2;
-    if (D == 2 && tiles * ((nM + chunk - 1) / chunk) < 1024) chunk = std::max(4, chunk / 2);
+    while (chunk > 8 && tiles * ((nM + chunk - 1) / chunk) < want) chunk /= 2;
+    if (D == 2 && tiles * ((nM + chunk - 1) / chunk) < want) chunk = std::max(4, chunk / 2);
     return std::min(chunk, std::max(nM, 1));
 }
 
-// Default step kernel per lattice and precision (measured on MI355X, 128^3
-// D3Q19 and 1024^2 D2Q9 cavities): the two-lane split doubles the waves per
-// SIMD where one lane per column runs a single wave (D3Q19 FP64: 155 KB of
-// LDS per tile) and pays its duplicated per-column work elsewhere.
-int default_step_kernel(int lattice, int dtype)
+// Default step kernel (measured on MI355X, 128^3 D3Q19 and 1024^2 D2Q9
+// cavities).  The two-lane split (3) doubles the waves per SIMD of the D3Q19
+// tile and wins wherever its registers fit the occupancy it is built for;
+// with a force field its face-force interpolation spills (D3Q19 FP64), and
+// in FP32 only the uniform field-free instance fits four waves per SIMD, so
+// those cases take the one-lane kernel (2).  D2Q9: the split everywhere.
+int default_step_kernel(int lattice, int dtype, bool uniform, bool field)
 {
-    if (lattice == DUGKS_D3Q19) return dtype == DUGKS_F64 ? 3 : 2;
-    return dtype == DUGKS_F64 ? 2 : 3;
+    if (lattice == DUGKS_D2Q9) return 3;
+    if (dtype == DUGKS_F64) return field ? 2 : 3;
+    return (uniform && !field) ? 3 : 2;
 }
 
 int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk);
@@ -635,8 +640,9 @@ int setup_fast(dugks_ctx* ctx)
     const char* env = getenv("DUGKS_FORCE_GENERAL");
     if (env && env[0] == '1') return DUGKS_OK;
     // 1: every face evaluated by both neighbours; 2: faces evaluated once;
-    // 3: faces once, velocity set split over two lanes per column
-    ctx->fast = default_step_kernel(ctx->cfg.lattice, ctx->cfg.dtype);
+    // 3: faces once, velocity set split over two lanes per column;
+    // 4: per launch, the default of default_step_kernel
+    ctx->fast = 4;
     const char* v = getenv("DUGKS_FUSED_VARIANT");
     if (v && v[0] == '1') ctx->fast = 1;
     if (v && v[0] == '2') ctx->fast = 2;
@@ -647,14 +653,23 @@ int setup_fast(dugks_ctx* ctx)
     return DUGKS_OK;
 }
 
+// the step kernel a launch with (without) a force field uses
+int resolve_step_kernel(const dugks_ctx* ctx, bool field)
+{
+    if (ctx->fast != 4) return ctx->fast;
+    const bool uni = ctx->cfg.dtype == DUGKS_F64 ? ctx->pd.uni != 0 : ctx->pf.uni != 0;
+    return default_step_kernel(ctx->cfg.lattice, ctx->cfg.dtype, uni, field);
+}
+
 int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, bool* handled)
 {
     *handled = false;
-    if (ctx->fast < 1 || ctx->fast > 3) return DUGKS_OK;
+    const int variant = resolve_step_kernel(ctx, force != nullptr);
+    if (variant < 1 || variant > 3) return DUGKS_OK;
     *handled = true;
-    const int chunk = pick_chunk(ctx);
-    if (ctx->fast == 3) return split_step(ctx, fin, fout, force, t, st, chunk);
-    if (ctx->fast == 2) {
+    const int chunk = pick_chunk(ctx, variant);
+    if (variant == 3) return split_step(ctx, fin, fout, force, t, st, chunk);
+    if (variant == 2) {
         if (ctx->cfg.lattice == DUGKS_D3Q19) {
             if (ctx->cfg.dtype == DUGKS_F64) return launch_fused2<D3Q19, double, 18, 14, 1, prefetch_planes<D3Q19, double>()>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
             return launch_fused2<D3Q19, float, 18, 14, 2, prefetch_planes<D3Q19, float>()>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
@@ -727,11 +742,11 @@ hipError_t split_batch_launch(int lattice, int dtype, int variant, const void* i
 
 // one batched step on the default step kernel of the lattice and precision
 // (so that batched and single-instance runs give identical states)
-hipError_t batch_step_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
-                             const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
-                             void* fout, const long long* step0, int step, hipStream_t st)
+hipError_t batch_step_launch(int lattice, int dtype, bool uniform, int variant, const void* insts,
+                             const long long* bstart, const BatchGeom* geom, int n, long long nblocks, const void* fin,
+                             const void* forces, void* fout, const long long* step0, int step, hipStream_t st)
 {
-    if (default_step_kernel(lattice, dtype) == 3)
+    if (default_step_kernel(lattice, dtype, uniform, forces != nullptr) == 3)
         return split_batch_launch(lattice, dtype, variant, insts, bstart, geom, n, nblocks, fin, forces, fout, step0,
                                   step, st);
 #define DUGKS_BATCH_ARGS insts, bstart, geom, n, nblocks, fin, forces, fout, step0, step, st

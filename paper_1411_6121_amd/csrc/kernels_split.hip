@@ -26,11 +26,25 @@
 namespace dugks {
 
 
-// value of the partner lane (same column, other half)
-template <typename T>
-__device__ __forceinline__ T partner(T v)
+// value of the partner lane (same column, other half): v_permlane32_swap
+// exchanges lanes 32..63 of its first operand with lanes 0..31 of its second;
+// with both operands = v the partner's value is the second result in the
+// lower half-wave and the first in the upper one.  Both lanes of a pair are
+// always active together.
+__device__ __forceinline__ unsigned partner_u32(unsigned v)
 {
-    return __shfl_xor(v, 32);
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __lane_id() < 32 ? r[1] : r[0];
+}
+__device__ __forceinline__ float partner(float v)
+{
+    return __builtin_bit_cast(float, partner_u32(__builtin_bit_cast(unsigned, v)));
+}
+__device__ __forceinline__ double partner(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = partner_u32((unsigned)b), hi = partner_u32((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // number of half-0 velocities crossing a face of axis A, and the slot of k
@@ -658,9 +672,12 @@ template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
 static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
                         hipStream_t st, int chunk)
 {
+    // FP32 D3Q19, uniform and field-free: fits four waves per SIMD (two
+    // tiles per CU) without spills
+    constexpr int MINW_UF = (LAT::D == 3 && sizeof(T) == 4) ? 4 : MINW;
     if (P.uni) {
         if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true, true>(ctx, P, fin, fout, force, t, st, chunk);
-        return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+        return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true>(ctx, P, fin, fout, force, t, st, chunk);
     }
     if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true, false>(ctx, P, fin, fout, force, t, st, chunk);
     return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, false>(ctx, P, fin, fout, force, t, st, chunk);

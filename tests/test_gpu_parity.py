@@ -38,11 +38,12 @@ VARIANTS = {"general": 0, "fused-twice": 1, "fused": 2, "split": 3}
 
 
 def default_kernel(cfg):
-    """the library's default step kernel (documented in dugks.h)"""
-    f64 = cfg.get("dtype", "f64") == "f64"
-    if cfg["lattice"] == 19:
-        return 3 if f64 else 2
-    return 2 if f64 else 3
+    """the library's default step kernel for a launch without a force field
+    (documented in dugks.h)"""
+    if cfg["lattice"] == 9 or cfg.get("dtype", "f64") == "f64":
+        return 3
+    uniform = all(m == 0 for m in cfg.get("mesh", (0, 0, 0)))
+    return 3 if uniform else 2
 
 
 def make_ctx(cfg, fb, variant=None, **kw):
