@@ -15,10 +15,10 @@ line:
              8 TB/s HBM peak; `traffic` = HBM bytes per launch measured with
              rocprofv3 counters (profiles/traffic.json), null when the kernel
              sources changed since
-  also       the same workload in FP32; 64 uneven D2Q9 instances advanced by
-             one batched launch per step (graph replay) vs 64 plain launches
-             per step; the adjoint step vs the forward step (D2Q9 256^2
-             periodic, FP64)
+  also       the same workload in FP32 and with the original-DUGKS
+             equilibrium; 64 uneven D2Q9 instances advanced by one batched
+             launch per step (graph replay) vs 64 plain launches per step;
+             the adjoint step vs the forward step (D2Q9 256^2 periodic, FP64)
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample
              of the same workload
 
@@ -377,6 +377,17 @@ def main():
             b32 = 2.0 * Q * 4 * cells
             also["f32"] = {"ms_per_step": round(ms32, 5), "mlups": round(cells / ms32 / 1e3, 2),
                            "hbm_frac": round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # the original-DUGKS equilibrium variant (general two-kernel path)
+        corig = dict(cfg, model=1)
+        f = torch.empty((Q,) + shp, dtype=M.torch_dtype(cfg), device="cuda")
+        g = torch.empty_like(f)
+        ctx = M.dugks_init(corig, f)
+        mso, _ = time_steps(ctx, corig, f, g, max(args.steps // 4, 10), max(args.warmup // 4, 2))
+        M.dugks_destroy(ctx)
+        del f, g
+        also["original_model"] = {"ms_per_step": round(mso, 5), "mlups": round(cells / mso / 1e3, 2),
+                                  "hbm_frac": round(bytes_per_step / (mso * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "kernel": "general (two launches)"}
         also["batched"] = bench_batched()
         also["adjoint"] = bench_adjoint()
         res["also"] = also

@@ -62,6 +62,10 @@ extern "C" {
 enum dugks_lattice { DUGKS_D2Q9 = 9, DUGKS_D3Q19 = 19 };
 enum dugks_dtype { DUGKS_F32 = 0, DUGKS_F64 = 1 };
 enum dugks_mesh_kind { DUGKS_UNIFORM = 0, DUGKS_TANH = 1 };
+/* equilibrium model: the paper's incompressible one (Eq. icfeq with
+ * Eq. macro_values) or the original DUGKS one (Eq. feq with
+ * rho u = sum xi f + rho G dt/2), kept for comparison */
+enum dugks_model { DUGKS_MODEL_INCOMPRESSIBLE = 0, DUGKS_MODEL_ORIGINAL = 1 };
 /* boundary kinds, one per domain side (-x,+x,-y,+y,-z,+z) */
 enum dugks_bc {
     DUGKS_PERIODIC = 0,     /* both sides of the axis must be periodic      */
@@ -83,6 +87,9 @@ enum dugks_bc {
  *               G(x, t) = g(t) (G + G^(x)), G^ the optional force field
  *   bc[6]       side kinds; uw[6][3] wall velocities; pw[6] wall pressures
  *               (pressure p = (rho - rho0) RT)
+ *   model       DUGKS_MODEL_INCOMPRESSIBLE (0, the paper's model) or
+ *               DUGKS_MODEL_ORIGINAL (1: runs on the general kernels; no
+ *               batched form, no adjoint: DUGKS_EUNSUPPORTED there)
  */
 typedef struct {
     int lattice;
@@ -97,6 +104,7 @@ typedef struct {
     int bc[6];
     double uw[6][3];
     double pw[6];
+    int model;
 } dugks_config;
 
 typedef struct dugks_ctx dugks_ctx;

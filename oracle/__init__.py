@@ -18,6 +18,7 @@ Configurations are plain dicts with the keys::
     bc        6 side codes (-x,+x,-y,+y,-z,+z): 0 periodic, 1 NEQ velocity,
               2 NEQ pressure, 3 bounce-back
     uw        6 x 3 wall velocities, pw  6 wall pressures
+    model     0 incompressible (default), 1 original DUGKS equilibrium
 
 Arrays: distributions ``f[q, z, y, x]``, vector fields ``v[d, z, y, x]``,
 scalar fields ``s[z, y, x]``; float64, C-contiguous.
@@ -52,6 +53,7 @@ class _Cfg(ctypes.Structure):
         ("bc", ctypes.c_int * 6),
         ("uw", (ctypes.c_double * 3) * 6),
         ("pw", ctypes.c_double * 6),
+        ("model", ctypes.c_int),
     ]
 
 
@@ -97,6 +99,7 @@ def _cfg(d: dict) -> _Cfg:
     c.dt = float(d["dt"])
     c.omega = float(d.get("omega", 0.0))
     c.phase = float(d.get("phase", 0.0))
+    c.model = int(d.get("model", 0))
     uw = d.get("uw", [[0.0] * 3] * 6)
     pw = d.get("pw", [0.0] * 6)
     for s in range(6):

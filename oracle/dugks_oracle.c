@@ -120,6 +120,7 @@ static int setup(octx* o, const oracle_cfg* cfg)
     if (o->Q < 0) return -1;
     o->D = (cfg->lattice == 9) ? 2 : 3;
     if (!(cfg->RT > 0) || !(cfg->tau > 0) || !(cfg->dt > 0) || !(cfg->rho0 > 0)) return -1;
+    if (cfg->model != 0 && cfg->model != 1) return -1;
     o->c = sqrt(3.0 * cfg->RT);
     for (int q = 0; q < o->Q; ++q)
         for (int a = 0; a < 3; ++a) o->xi[q][a] = o->c * o->e[q][a];
@@ -179,13 +180,22 @@ static int setup(octx* o, const oracle_cfg* cfg)
 /* point-local formulas                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* Eq. (icfeq): W_q { rho + rho0 [ xi.u/RT + (xi.u)^2/(2 RT^2) - |u|^2/(2 RT) ] } */
+/* Eq. (icfeq): W_q { rho + rho0 [ xi.u/RT + (xi.u)^2/(2 RT^2) - |u|^2/(2 RT) ] }
+ * (model 0), or the original Eq. (feq):
+ *   W_q rho [ 1 + xi.u/RT + (xi.u)^2/(2 RT^2) - |u|^2/(2 RT) ]      (model 1) */
 static double feq_q(const octx* o, const oracle_cfg* cfg, int q, double rho, const double* u)
 {
     double RT = cfg->RT, xu = 0.0, uu = 0.0;
     for (int a = 0; a < o->D; ++a) { xu += o->xi[q][a] * u[a]; uu += u[a] * u[a]; }
-    return o->W[q] * (rho + cfg->rho0 * (xu / RT + xu * xu / (2.0 * RT * RT) - uu / (2.0 * RT)));
+    const double poly = xu / RT + xu * xu / (2.0 * RT * RT) - uu / (2.0 * RT);
+    if (cfg->model == 1) return o->W[q] * rho * (1.0 + poly);
+    return o->W[q] * (rho + cfg->rho0 * poly);
 }
+
+/* density that multiplies u in the momentum of the model: rho0 in
+ * Eq. (macro_values) (model 0), rho in the original model's
+ * rho u = sum xi f + rho G dt/2 (model 1) */
+static double mom_density(const oracle_cfg* cfg, double rho) { return cfg->model == 1 ? rho : cfg->rho0; }
 
 /* Eq. (S), evaluated with the incompressible equilibrium as the Appendix
  * does: S = G.(xi - u)/RT feq */
@@ -448,7 +458,8 @@ int oracle_step(const oracle_cfg* cfg, const double* fin, double* fout, const do
                     for (int a = 0; a < D; ++a) m[a] += o.xi[q][a] * fq;
                 }
                 accel_cell(&o, cfg, Gext, ce, gt, G);
-                for (int a = 0; a < D; ++a) u[a] = (m[a] + rho0 * G[a] * dt / 2.0) / rho0;
+                const double rm = mom_density(cfg, rho);
+                for (int a = 0; a < D; ++a) u[a] = (m[a] + rm * G[a] * dt / 2.0) / rm;
                 for (int q = 0; q < Q; ++q)
                     fp[ce * Q + q] = A1 * fin[q * nc + ci] + B1 * feq_q(&o, cfg, q, rho, u) +
                                      C1 * src_q(&o, cfg, q, rho, u, G);
@@ -587,7 +598,8 @@ int oracle_step(const oracle_cfg* cfg, const double* fin, double* fout, const do
                             for (int b = 0; b < D; ++b) m[b] += o.xi[q][b] * Fo[q];
                         }
                         accel_face(&o, cfg, Gext, a, co, gth, Gb);
-                        for (int b = 0; b < D; ++b) uc[b] = (m[b] + rho0 * Gb[b] * h / 2.0) / rho0;
+                        const double rm = mom_density(cfg, rc);
+                        for (int b = 0; b < D; ++b) uc[b] = (m[b] + rm * Gb[b] * h / 2.0) / rm;
                         double ra, ua[3] = {0, 0, 0};
                         if (bc == OR_NEQ_VELOCITY) {
                             ra = rc;
@@ -620,7 +632,8 @@ int oracle_step(const oracle_cfg* cfg, const double* fin, double* fout, const do
                         for (int b = 0; b < D; ++b) m[b] += o.xi[q][b] * Fb[q];
                     }
                     accel_face(&o, cfg, Gext, a, c, gth, G);
-                    for (int b = 0; b < D; ++b) u[b] = (m[b] + rho0 * G[b] * h / 2.0) / rho0;
+                    const double rm = mom_density(cfg, rho);
+                    for (int b = 0; b < D; ++b) u[b] = (m[b] + rm * G[b] * h / 2.0) / rm;
                     for (int q = 0; q < Q; ++q)
                         Fb[q] = A7 * Fb[q] + B7 * feq_q(&o, cfg, q, rho, u) + C7 * src_q(&o, cfg, q, rho, u, G);
                 }
@@ -666,7 +679,8 @@ int oracle_step(const oracle_cfg* cfg, const double* fin, double* fout, const do
 }
 
 /* ------------------------------------------------------------------------ */
-/* step 10 / outputs: Eq. (macro_values), p = (rho - rho0) RT                 */
+/* step 10 / outputs: Eq. (macro_values), p = (rho - rho0) RT (gauge        */
+/* pressure, both models)                                                    */
 /* ------------------------------------------------------------------------ */
 int oracle_moments(const oracle_cfg* cfg, const double* f, const double* force, double t,
                    double* rho, double* u, double* p, double* totals)
@@ -694,7 +708,8 @@ int oracle_moments(const oracle_cfg* cfg, const double* f, const double* force, 
                 double k2 = 0.0;
                 for (int a = 0; a < D; ++a) {
                     double G = gt * (cfg->G[a] + (force ? force[a * nc + ci] : 0.0));
-                    uu[a] = (m[a] + cfg->rho0 * G * cfg->dt / 2.0) / cfg->rho0;
+                    const double rm = mom_density(cfg, r);
+                    uu[a] = (m[a] + rm * G * cfg->dt / 2.0) / rm;
                     k2 += uu[a] * uu[a];
                     if (u) u[a * nc + ci] = uu[a];
                     tot[1 + a] += V * m[a];
@@ -740,6 +755,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                         const double* lam, double* lam_out, double* grad_force)
 {
     octx o;
+    if (cfg->model != 0) return -2; /* derived for the incompressible model */
     if (setup(&o, cfg)) return -1;
     for (int a = 0; a < o.D; ++a)
         if (!o.per[a]) { ctx_free(&o); return -2; }
@@ -1000,6 +1016,7 @@ int oracle_init_adjoint(const oracle_cfg* cfg, const double* u, const double* fo
                         const double* lam0, double* grad_u, double* grad_force)
 {
     octx o;
+    if (cfg->model != 0) return -2; /* derived for the incompressible model */
     if (setup(&o, cfg)) return -1;
     const int D = o.D, Q = o.Q;
     const long nc = ncells(&o);

@@ -40,6 +40,9 @@ typedef struct {
     int bc[6];          /* sides -x,+x,-y,+y,-z,+z */
     double uw[6][3];    /* wall velocity per side (velocity BCs) */
     double pw[6];       /* wall pressure per side (pressure BC) */
+    int model;          /* 0: incompressible model, Eq. (icfeq) with
+                           Eq. (macro_values); 1: original DUGKS, Eq. (feq)
+                           with rho u = sum xi f + rho G dt/2 */
 } oracle_cfg;
 
 /* lattice table: e[q*3+a] in {-1,0,1}, w[q]; returns Q or -1 */

@@ -9,7 +9,8 @@ fallback: without the built library every call raises.
 Configurations are plain dicts (keys as in ``dugks_config``)::
 
     lattice 9|19, dtype "f32"|"f64", n (3), L (3), mesh (3), k_stretch,
-    rho0, RT, tau, dt, G (3), omega, phase, bc (6), uw (6x3), pw (6)
+    rho0, RT, tau, dt, G (3), omega, phase, bc (6), uw (6x3), pw (6),
+    model (0 incompressible, 1 original DUGKS equilibrium)
 
 Tensors: state ``[Q, nz, ny, nx]``, vector fields ``[D, nz, ny, nx]``,
 scalars ``[nz, ny, nx]``, all contiguous on the CUDA (HIP) device, in the
@@ -52,6 +53,7 @@ class Config(ctypes.Structure):
         ("bc", ctypes.c_int * 6),
         ("uw", (ctypes.c_double * 3) * 6),
         ("pw", ctypes.c_double * 6),
+        ("model", ctypes.c_int),
     ]
 
 
@@ -123,6 +125,7 @@ def config(d: dict) -> Config:
     c.dt = float(d["dt"])
     c.omega = float(d.get("omega", 0.0))
     c.phase = float(d.get("phase", 0.0))
+    c.model = int(d.get("model", 0))
     uw = d.get("uw", [[0.0] * 3] * 6)
     pw = d.get("pw", [0.0] * 6)
     for s in range(6):

@@ -175,6 +175,8 @@ extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t
         if (cfgs[i].lattice != cfgs[0].lattice || cfgs[i].dtype != cfgs[0].dtype)
             return bfail(nullptr, DUGKS_EINVAL, "all instances must share lattice and dtype");
         if (offsets[i] < 0) return bfail(nullptr, DUGKS_EINVAL, "negative offset");
+        if (cfgs[i].model != DUGKS_MODEL_INCOMPRESSIBLE)
+            return bfail(nullptr, DUGKS_EUNSUPPORTED, "batched instances use the incompressible model");
     }
     dugks_batch* b = new dugks_batch();
     b->n = n;

@@ -69,6 +69,7 @@ int validate(const dugks_config* c, std::string& why)
     long long cells = 1;
     for (int a = 0; a < D; ++a) cells *= (long long)(c->n[a] + 2);
     if (cells * c->lattice > (1LL << 40)) { why = "problem too large"; return DUGKS_EINVAL; }
+    if (c->model != DUGKS_MODEL_INCOMPRESSIBLE && c->model != DUGKS_MODEL_ORIGINAL) { why = "unknown model"; return DUGKS_EINVAL; }
     if (!finite_pos(c->rho0) || !finite_pos(c->RT) || !finite_pos(c->tau) || !finite_pos(c->dt)) {
         why = "rho0, RT, tau, dt must be positive and finite";
         return DUGKS_EINVAL;
@@ -201,6 +202,10 @@ void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& me
         P.eqB = (T)(r0 * cc / RT);
         P.eqC = (T)(r0 * cc * cc / (2.0 * RT * RT));
         P.sG = (T)(cc / RT);
+        P.orig = c->model == DUGKS_MODEL_ORIGINAL ? 1 : 0;
+        P.hRT = (T)(1.0 / (2.0 * RT));
+        P.cRT = (T)(cc / RT);
+        P.c2RT2 = (T)(cc * cc / (2.0 * RT * RT));
     }
     P.uni = 1;
     for (int a = 0; a < D; ++a) {
@@ -263,38 +268,38 @@ extern "C" double dugks_dt_from_cfl(const dugks_config* cfg, double cfl)
 // ---------------------------------------------------------------------------
 namespace dugks {
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG>
 __global__ __launch_bounds__(256) void k_phi_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                  T* __restrict__ phi, T gt)
 {
     const Inst<T>& P = *Pp;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P.ne) return;
-    phi_ext_body<LAT, T>(P, e, f, force, phi, gt);
+    phi_ext_body<LAT, T, ORIG>(P, e, f, force, phi, gt);
 }
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG>
 __global__ __launch_bounds__(256) void k_update_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                     const T* __restrict__ phi, T* __restrict__ fout, T gth)
 {
     const Inst<T>& P = *Pp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nc) return;
-    update_body<LAT, T>(P, c, f, force, phi, fout, gth);
+    update_body<LAT, T, ORIG>(P, c, f, force, phi, fout, gth);
 }
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG>
 __global__ __launch_bounds__(256) void k_init_one(const Inst<T>* __restrict__ Pp, const T* rho, const T* u, const T* force, T gt,
                                                   T* fout)
 {
     const Inst<T>& P = *Pp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nc) return;
-    init_body<LAT, T>(P, c, rho, u, force, gt, fout);
+    init_body<LAT, T, ORIG>(P, c, rho, u, force, gt, fout);
 }
 
 // macroscopic fields and per-block partial totals (Appendix step 10)
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG>
 __global__ __launch_bounds__(256) void k_moments_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                      T gt, T* rho_o, T* u_o, T* p_o, double* partial)
 {
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(256) void k_moments_one(const Inst<T>* __restrict__
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             const T G = gt * (P.G0[a] + (force ? force[(long long)a * P.nc + ci] : T(0)));
-            const T ua = P.c * j[a] / P.rho0 + P.h * G;
+            const T ua = vel_from<T, ORIG>(P, rho, j[a], G, P.h);
             if (u_o) u_o[(long long)a * P.nc + ci] = ua;
             k2 += (double)ua * (double)ua;
             loc[1 + a] = V * (double)(P.c * j[a]);
@@ -375,10 +380,19 @@ int launch_step_general(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
                         double t, hipStream_t st)
 {
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
-    hipLaunchKernelGGL((k_phi_one<LAT, T>), dim3(nblocks(P.ne, 256)), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
-                       (const T*)fin, (const T*)force, (T*)ctx->phi, gt);
-    hipLaunchKernelGGL((k_update_one<LAT, T>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
-                       (const T*)fin, (const T*)force, (const T*)ctx->phi, (T*)fout, gth);
+    if (P.orig) {
+        hipLaunchKernelGGL((k_phi_one<LAT, T, true>), dim3(nblocks(P.ne, 256)), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)fin, (const T*)force, (T*)ctx->phi, gt);
+        hipLaunchKernelGGL((k_update_one<LAT, T, true>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)fin, (const T*)force, (const T*)ctx->phi, (T*)fout,
+                           gth);
+    } else {
+        hipLaunchKernelGGL((k_phi_one<LAT, T, false>), dim3(nblocks(P.ne, 256)), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)fin, (const T*)force, (T*)ctx->phi, gt);
+        hipLaunchKernelGGL((k_update_one<LAT, T, false>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)fin, (const T*)force, (const T*)ctx->phi, (T*)fout,
+                           gth);
+    }
     return hip_check(ctx, hipGetLastError(), "step launch");
 }
 
@@ -386,8 +400,14 @@ template <class LAT, typename T>
 int launch_init(dugks_ctx* ctx, const Inst<T>& P, const void* rho, const void* u, const void* force, double t0,
                 void* fout, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_init_one<LAT, T>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev, (const T*)rho,
-                       (const T*)u, (const T*)force, tfac(P, t0), (T*)fout);
+    if (P.orig)
+        hipLaunchKernelGGL((k_init_one<LAT, T, true>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)rho, (const T*)u, (const T*)force, tfac(P, t0),
+                           (T*)fout);
+    else
+        hipLaunchKernelGGL((k_init_one<LAT, T, false>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)rho, (const T*)u, (const T*)force, tfac(P, t0),
+                           (T*)fout);
     return hip_check(ctx, hipGetLastError(), "init launch");
 }
 
@@ -396,9 +416,12 @@ int launch_moments(dugks_ctx* ctx, const Inst<T>& P, const void* f, const void* 
                    void* u, void* p, hipStream_t st)
 {
     const unsigned nb = nblocks(P.nc, 256);
-    hipLaunchKernelGGL((k_moments_one<LAT, T>), dim3(nb), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev, (const T*)f,
-                       (const T*)force,
-                       tfac(P, t), (T*)rho, (T*)u, (T*)p, ctx->partial);
+    if (P.orig)
+        hipLaunchKernelGGL((k_moments_one<LAT, T, true>), dim3(nb), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
+                           (const T*)f, (const T*)force, tfac(P, t), (T*)rho, (T*)u, (T*)p, ctx->partial);
+    else
+        hipLaunchKernelGGL((k_moments_one<LAT, T, false>), dim3(nb), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
+                           (const T*)f, (const T*)force, tfac(P, t), (T*)rho, (T*)u, (T*)p, ctx->partial);
     hipLaunchKernelGGL(k_reduce6, dim3(1), dim3(256), 0, st, (const double*)ctx->partial, (int)nb, ctx->totals_dev);
     return hip_check(ctx, hipGetLastError(), "moments launch");
 }

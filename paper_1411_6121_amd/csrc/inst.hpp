@@ -55,6 +55,10 @@ struct Inst {
     // factored Eqs. (icfeq), (S): eqH = rho0 / (2 RT), eqB = rho0 c / RT,
     // eqC = rho0 c^2 / (2 RT^2), sG = c / RT
     T crho, invRT, eqH, eqB, eqC, sG;
+    // model 1 (original DUGKS, Eq. feq): the same constants per unit density
+    // (hRT = 1 / (2 RT), cRT = c / RT, c2RT2 = c^2 / (2 RT^2)); orig = 1
+    int orig;
+    T hRT, cRT, c2RT2;
     // uniform mesh (every active axis): uni = 1 and per axis, with
     // Delta = L / N, the face weight is 1/2 and the derivative coefficients
     // are ugn = 1 / Delta (normal difference), uct = 1 / (4 Delta) (the face's
@@ -119,10 +123,14 @@ __device__ __forceinline__ T src_fac(int q, const T* u, const T* G, T c, T invRT
 template <typename T>
 struct EqPt {
     T a, g;
+    T B, C;  // per point in the original model (rho cRT, rho c2RT2)
     T u[3], G[3];
 };
 
-template <class LAT, typename T>
+// ORIG: the original model's Eq. (feq) = W_q rho [1 + xi.u/RT + (xi.u)^2 /
+// (2 RT^2) - |u|^2/(2 RT)], i.e. a = rho (1 - hRT |u|^2), and the eu
+// coefficients carry rho instead of rho0.
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ EqPt<T> eq_point(const Inst<T>& P, T rho, const T* u, const T* G)
 {
     EqPt<T> E;
@@ -137,7 +145,15 @@ __device__ __forceinline__ EqPt<T> eq_point(const Inst<T>& P, T rho, const T* u,
         uu += E.u[a] * E.u[a];
         gu += E.G[a] * E.u[a];
     }
-    E.a = rho - P.eqH * uu;
+    if constexpr (ORIG) {
+        E.a = rho - rho * P.hRT * uu;
+        E.B = rho * P.cRT;
+        E.C = rho * P.c2RT2;
+    } else {
+        E.a = rho - P.eqH * uu;
+        E.B = P.eqB;
+        E.C = P.eqC;
+    }
     E.g = gu * P.invRT;
     return E;
 }
@@ -155,11 +171,23 @@ __device__ __forceinline__ T e_dot(int q, const T* v)
     return s;
 }
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ T feq_pt(const Inst<T>& P, const EqPt<T>& E, int q)
 {
     const T eu = e_dot<LAT, T>(q, E.u);
-    return T(LAT::w(q)) * (E.a + eu * (P.eqB + P.eqC * eu));
+    if constexpr (ORIG) return T(LAT::w(q)) * (E.a + eu * (E.B + E.C * eu));
+    else return T(LAT::w(q)) * (E.a + eu * (P.eqB + P.eqC * eu));
+}
+
+// velocity from the momentum moment j = sum e f (a sum of the state's
+// components), the acceleration G and its time weight hw (dt/2 at cells,
+// h/2 at faces): u = c j / rho0 + hw G (Eq. macro_values), or, in the
+// original model, rho u = c j + rho hw G
+template <typename T, bool ORIG = false>
+__device__ __forceinline__ T vel_from(const Inst<T>& P, T rho, T j, T G, T hw)
+{
+    if constexpr (ORIG) return P.c * j / rho + hw * G;
+    else return P.crho * j + hw * G;
 }
 
 // S_q / feq_q

@@ -33,7 +33,7 @@ __device__ __forceinline__ long long int_idx(const Inst<T>& P, int i, int j, int
 
 // f-bar-plus of one interior cell (Appendix step 1) from its state fv[Q]
 // and its force-field values fg[D] (used if has_field)
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void phi_from(const Inst<T>& P, const T (&fv)[LAT::Q], const T (&fg)[3], bool has_field,
                                          T gt, T* out)
 {
@@ -52,19 +52,19 @@ __device__ __forceinline__ void phi_from(const Inst<T>& P, const T (&fv)[LAT::Q]
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
-        u[a] = P.crho * j[a] + P.h * G[a];
+        u[a] = vel_from<T, ORIG>(P, rho, j[a], G[a], P.h);
     }
-    const EqPt<T> E = eq_point<LAT, T>(P, rho, u, G);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, u, G);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T fe = feq_pt<LAT, T>(P, E, q);
+        const T fe = feq_pt<LAT, T, ORIG>(P, E, q);
         const T S = srcf_pt<LAT, T>(P, E, q) * fe;
         out[q] = fv[q] + P.B1 * (fe - fv[q]) + P.C1 * S;
     }
 }
 
 // the same, loading the cell's state and force field from HBM
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__ f, const T* __restrict__ force, long long ci,
                          T gt, T* out)
 {
@@ -76,10 +76,10 @@ __device__ __forceinline__ void phi_cell(const Inst<T>& P, const T* __restrict__
 #pragma unroll
         for (int a = 0; a < D; ++a) fg[a] = force[(long long)a * P.nc + ci];
     }
-    phi_from<LAT, T>(P, fv, fg, force != nullptr, gt, out);
+    phi_from<LAT, T, ORIG>(P, fv, fg, force != nullptr, gt, out);
 }
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void phi_ext_body(const Inst<T>& P, long long e, const T* __restrict__ f, const T* __restrict__ force,
                              T* __restrict__ phi, T gt)
 {
@@ -116,7 +116,7 @@ __device__ __forceinline__ void phi_ext_body(const Inst<T>& P, long long e, cons
     }
     T acc[Q];
     if (cnt[0] * cnt[1] * cnt[2] == 1) {
-        phi_cell<LAT, T>(P, f, force, int_idx(P, idx[0][0], idx[1][0], idx[2][0]), gt, acc);
+        phi_cell<LAT, T, ORIG>(P, f, force, int_idx(P, idx[0][0], idx[1][0], idx[2][0]), gt, acc);
     } else {
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[q] = T(0);
@@ -124,7 +124,7 @@ __device__ __forceinline__ void phi_ext_body(const Inst<T>& P, long long e, cons
             for (int i1 = 0; i1 < cnt[1]; ++i1)
                 for (int i0 = 0; i0 < cnt[0]; ++i0) {
                     T tmp[Q];
-                    phi_cell<LAT, T>(P, f, force, int_idx(P, idx[0][i0], idx[1][i1], idx[2][i2]), gt, tmp);
+                    phi_cell<LAT, T, ORIG>(P, f, force, int_idx(P, idx[0][i0], idx[1][i1], idx[2][i2]), gt, tmp);
                     const T w = wt[0][i0] * wt[1][i1] * wt[2][i2];
 #pragma unroll
                     for (int q = 0; q < Q; ++q) acc[q] += w * tmp[q];
@@ -205,7 +205,7 @@ __device__ __forceinline__ CellMetric<T> load_metric(const Inst<T>& P, int a, in
 }
 
 // interface moments (Appendix step 6): rho, u = j/rho0 + h/2 G
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void face_moments(const Inst<T>& P, const T* fb, const T* G, T& rho, T* u)
 {
     rho = T(0);
@@ -220,7 +220,7 @@ __device__ __forceinline__ void face_moments(const Inst<T>& P, const T* fb, cons
         }
     }
 #pragma unroll
-    for (int a = 0; a < LAT::D; ++a) u[a] = P.crho * j[a] + T(0.5) * P.h * G[a];
+    for (int a = 0; a < LAT::D; ++a) u[a] = vel_from<T, ORIG>(P, rho, j[a], G[a], T(0.5) * P.h);
 #pragma unroll
     for (int a = LAT::D; a < 3; ++a) u[a] = T(0);
 }
@@ -234,22 +234,22 @@ struct NeqInfo {
     T neq[LAT::Q];
 };
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void neq_capture(const Inst<T>& P, int a, const T* oppf, const T* Gopp,
                                             NeqInfo<LAT, T>& I)
 {
-    face_moments<LAT, T>(P, oppf, Gopp, I.rc, I.uc);
-    const EqPt<T> E = eq_point<LAT, T>(P, I.rc, I.uc, nullptr);
+    face_moments<LAT, T, ORIG>(P, oppf, Gopp, I.rc, I.uc);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, I.rc, I.uc, nullptr);
 #pragma unroll
     for (int q = 0; q < LAT::Q; ++q) {
         if (LAT::e(q, a) == 0) continue;
-        I.neq[q] = oppf[q] - feq_pt<LAT, T>(P, E, q);
+        I.neq[q] = oppf[q] - feq_pt<LAT, T, ORIG>(P, E, q);
     }
 }
 
 // Appendix step 5 on a wall face of side s (Eqs. BB, NEQ), in place on the
 // reconstructed values, for the velocities entering the domain.
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, const NeqInfo<LAT, T>& I)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
@@ -277,25 +277,25 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = I.uc[d];
     }
-    const EqPt<T> E = eq_point<LAT, T>(P, ra, ua, nullptr);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, ra, ua, nullptr);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (LAT::e(q, a) * sg >= 0) continue;
-        wall[q] = feq_pt<LAT, T>(P, E, q) + I.neq[q];
+        wall[q] = feq_pt<LAT, T, ORIG>(P, E, q) + I.neq[q];
     }
 }
 
 // Appendix step 7 for the velocities that cross a face of axis a
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void face_original(const Inst<T>& P, int a, T* fb, const T* G)
 {
     T rho, u[3];
-    face_moments<LAT, T>(P, fb, G, rho, u);
-    const EqPt<T> E = eq_point<LAT, T>(P, rho, u, G);
+    face_moments<LAT, T, ORIG>(P, fb, G, rho, u);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, u, G);
 #pragma unroll
     for (int q = 0; q < LAT::Q; ++q) {
         if (LAT::e(q, a) == 0) continue;
-        const T fe = feq_pt<LAT, T>(P, E, q);
+        const T fe = feq_pt<LAT, T, ORIG>(P, E, q);
         const T S = srcf_pt<LAT, T>(P, E, q) * fe;
         fb[q] = fb[q] + P.B7 * (fe - fb[q]) + P.C7 * S;
     }
@@ -331,7 +331,7 @@ __device__ __forceinline__ void recon_face_ct(const Inst<T>& P, const ACC& ph, b
     }
 }
 
-template <class LAT, typename T, class ACC, int A>
+template <class LAT, typename T, class ACC, int A, bool ORIG = false>
 __device__ __forceinline__ void axis_fluxes_ct(const Inst<T>& P, const ACC& ph, const T* __restrict__ force,
                                                const int* ci, T gth, const CellMetric<T>& mx,
                                                const CellMetric<T>& my, const CellMetric<T>& mz, T* acc)
@@ -352,9 +352,9 @@ __device__ __forceinline__ void axis_fluxes_ct(const Inst<T>& P, const ACC& ph, 
         recon_face_ct<LAT, T, ACC, A>(P, ph, upper, ma, mx, my, mz, fb);
         face_force<LAT, T>(P, force, A, upper ? ca + 1 : ca, upper ? ma.wu : ma.wl, ci, gth, G);
         const bool wall_here = upper ? whi : wlo;
-        if (k == 0 && (wlo != whi)) neq_capture<LAT, T>(P, A, fb, G, info);
-        if (wall_here) wall_rule<LAT, T>(P, upper ? 2 * A + 1 : 2 * A, fb, info);
-        face_original<LAT, T>(P, A, fb, G);
+        if (k == 0 && (wlo != whi)) neq_capture<LAT, T, ORIG>(P, A, fb, G, info);
+        if (wall_here) wall_rule<LAT, T, ORIG>(P, upper ? 2 * A + 1 : 2 * A, fb, info);
+        face_original<LAT, T, ORIG>(P, A, fb, G);
         const T s = ma.fdx * P.c;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -463,17 +463,17 @@ __device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const
 // updated state on exit.  Faces are taken one at a time; on a wall axis the
 // opposite (interior) face is evaluated first so that the NEQ rule can use
 // its moments and non-equilibrium part.
-template <class LAT, typename T, class ACC>
+template <class LAT, typename T, class ACC, bool ORIG = false>
 __device__ __forceinline__ void cell_fluxes(const Inst<T>& P, const ACC& ph, const T* __restrict__ force,
                                             const int* ci, T gth, const CellMetric<T> cx, const CellMetric<T> cy,
                                             const CellMetric<T> cz, T* acc)
 {
-    axis_fluxes_ct<LAT, T, ACC, 0>(P, ph, force, ci, gth, cx, cy, cz, acc);
-    axis_fluxes_ct<LAT, T, ACC, 1>(P, ph, force, ci, gth, cx, cy, cz, acc);
-    if constexpr (LAT::D == 3) axis_fluxes_ct<LAT, T, ACC, 2>(P, ph, force, ci, gth, cx, cy, cz, acc);
+    axis_fluxes_ct<LAT, T, ACC, 0, ORIG>(P, ph, force, ci, gth, cx, cy, cz, acc);
+    axis_fluxes_ct<LAT, T, ACC, 1, ORIG>(P, ph, force, ci, gth, cx, cy, cz, acc);
+    if constexpr (LAT::D == 3) axis_fluxes_ct<LAT, T, ACC, 2, ORIG>(P, ph, force, ci, gth, cx, cy, cz, acc);
 }
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void update_body(const Inst<T>& P, long long cidx, const T* __restrict__ f, const T* __restrict__ force,
                             const T* __restrict__ phi, T* __restrict__ fout, T gth)
 {
@@ -494,17 +494,16 @@ __device__ __forceinline__ void update_body(const Inst<T>& P, long long cidx, co
     const CellMetric<T> cx = load_metric(P, 0, ci[0]);
     const CellMetric<T> cy = load_metric(P, 1, ci[1]);
     const CellMetric<T> cz = LAT::D == 3 ? load_metric(P, 2, ci[2]) : cy;
-    cell_fluxes<LAT, T>(P, ph, force, ci, gth, cx, cy, cz, acc);
+    cell_fluxes<LAT, T, GlobalPhi<LAT, T>, ORIG>(P, ph, force, ci, gth, cx, cy, cz, acc);
 #pragma unroll
     for (int q = 0; q < Q; ++q) fout[(long long)q * P.nc + cidx] = acc[q];
 }
 
-template <class LAT, typename T>
+template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void init_body(const Inst<T>& P, long long ci, const T* rho, const T* u, const T* force, T gt,
                           T* fout)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    const T invRT = T(1) / P.RT;
     const T r = rho ? rho[ci] : P.rho0;
     T uu[3] = {T(0), T(0), T(0)}, G[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -512,10 +511,11 @@ __device__ __forceinline__ void init_body(const Inst<T>& P, long long ci, const 
         if (u) uu[a] = u[(long long)a * P.nc + ci];
         G[a] = gt * (P.G0[a] + (force ? force[(long long)a * P.nc + ci] : T(0)));
     }
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, r, uu, G);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T fe = feq_q<LAT, T>(q, r, uu, P.rho0, P.c, invRT);
-        fout[(long long)q * P.nc + ci] = fe - P.h * src_fac<LAT, T>(q, uu, G, P.c, invRT) * fe;
+        const T fe = feq_pt<LAT, T, ORIG>(P, E, q);
+        fout[(long long)q * P.nc + ci] = fe - P.h * srcf_pt<LAT, T>(P, E, q) * fe;
     }
 }
 

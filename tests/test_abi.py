@@ -60,7 +60,7 @@ def base_cfg(**kw):
 @pytest.mark.parametrize("bad", [
     dict(lattice=27), dict(n=(8, 8, 2)), dict(n=(0, 8, 1)), dict(tau=0.0), dict(dt=-1.0), dict(RT=float("nan")),
     dict(bc=(1, 0, 0, 0, 0, 0)), dict(bc=(0, 0, 1, 1, 0, 0), n=(8, 1, 1)), dict(mesh=(1, 0, 0), k_stretch=0.0),
-    dict(bc=(7, 7, 0, 0, 0, 0)), dict(L=(0.0, 8.0, 1.0)),
+    dict(bc=(7, 7, 0, 0, 0, 0)), dict(L=(0.0, 8.0, 1.0)), dict(model=2),
 ])
 def test_invalid_configurations_are_rejected(bad):
     with pytest.raises(M.DugksError) as ei:
@@ -85,3 +85,15 @@ def test_dt_from_cfl():
     import oracle as O
     X, _ = O.mesh(dict(d, lattice=9), 0)
     assert M.dugks_dt_from_cfl(d, 0.5) == pytest.approx(0.5 * (X[1] - X[0]) / 10.0, rel=1e-14)
+
+
+def test_batch_rejects_the_original_model_without_device():
+    # validation precedes any device work: the batched form is for the
+    # incompressible model only
+    lib = M.load()
+    cfg = M.config(base_cfg(model=1))
+    arr = (M.Config * 1)(cfg)
+    offs = (ctypes.c_int64 * 1)(0)
+    h = ctypes.c_void_p()
+    rc = lib.dugks_batch_create(arr, 1, offs, None, ctypes.byref(h))
+    assert rc == M.EUNSUPPORTED and not h.value
