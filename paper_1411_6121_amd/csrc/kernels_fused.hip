@@ -382,7 +382,11 @@ __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restric
     }
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
-            __syncthreads();  // ring slot of z+1 and the face buffers were read by the last update
+            // No barrier needed here: the ring slot of z+1 (= z-2) was last
+            // read by the faces of plane z-1, which every wave finished before
+            // the barrier that precedes the update of z-1; the face buffers
+            // are rewritten only after the barrier that ends this plane's
+            // computation, by which time every wave has left that update.
             if (!computed(z + 1)) {
                 ghost_plane(z + 1, z, z - 1, P.rhi[M]);
             } else {
