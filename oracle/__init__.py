@@ -7,7 +7,7 @@ TEST INFRASTRUCTURE ONLY.  The product package never imports this module; only
 
 Configurations are plain dicts with the keys::
 
-    lattice   9 (D2Q9) or 19 (D3Q19)
+    lattice   9 (D2Q9), 19 (D3Q19) or 27 (D3Q27)
     n         (nx, ny, nz)            nz = 1 for D2Q9
     L         (Lx, Ly, Lz)
     mesh      (kx, ky, kz)            0 uniform, 1 tanh-stretched, per axis

@@ -25,7 +25,7 @@
 #include <omp.h>
 #endif
 
-#define MAXQ 19
+#define MAXQ 27
 
 /* ------------------------------------------------------------------------ */
 /* derived context                                                           */
@@ -62,9 +62,10 @@ static void ctx_free(octx* o)
  * (the printed 1/3 is a misprint: the printed D2Q9 and D3Q27 weights are
  * products of 2/3 and 1/6, and the weights must sum to one).
  * D2Q9 is the tensor product in the paper's order (e_x outer, e_y inner).
- * D3Q19 (not in the paper, which uses D3Q27) keeps the tensor-product order
- * e_x outer, e_y, e_z inner and drops the eight |e|^2 = 3 corners, with
- * weights 1/3, 1/18, 1/36. */
+ * D3Q27 is the paper's 3-D set (Sec. II.C): the full tensor product, e_x
+ * outer, e_y, e_z inner, weights products of the 1-D weights.
+ * D3Q19 (not in the paper) keeps the same order and drops the eight
+ * |e|^2 = 3 corners, with weights 1/3, 1/18, 1/36. */
 static int make_lattice(int lattice, int e[MAXQ][3], double W[MAXQ], int opp[MAXQ])
 {
     int Q = 0;
@@ -84,6 +85,15 @@ static int make_lattice(int lattice, int e[MAXQ][3], double W[MAXQ], int opp[MAX
                     if (m == 3) continue;
                     e[Q][0] = ex; e[Q][1] = ey; e[Q][2] = ez;
                     W[Q] = (m == 0) ? 1.0 / 3.0 : (m == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+                    ++Q;
+                }
+    } else if (lattice == 27) {
+        const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+        for (int ex = -1; ex <= 1; ++ex)
+            for (int ey = -1; ey <= 1; ++ey)
+                for (int ez = -1; ez <= 1; ++ez) {
+                    e[Q][0] = ex; e[Q][1] = ey; e[Q][2] = ez;
+                    W[Q] = w1[ex + 1] * w1[ey + 1] * w1[ez + 1];
                     ++Q;
                 }
     } else {

@@ -16,6 +16,10 @@ def lattice(lat):
         w1 = {-1: 1 / 6, 0: 2 / 3, 1: 1 / 6}
         es = [(ex, ey, 0) for ex in (-1, 0, 1) for ey in (-1, 0, 1)]
         W = [w1[ex] * w1[ey] for ex, ey, _ in es]
+    elif lat == 27:
+        w1 = {-1: 1 / 6, 0: 2 / 3, 1: 1 / 6}
+        es = [(ex, ey, ez) for ex in (-1, 0, 1) for ey in (-1, 0, 1) for ez in (-1, 0, 1)]
+        W = [w1[ex] * w1[ey] * w1[ez] for ex, ey, ez in es]
     else:
         es = [(ex, ey, ez) for ex in (-1, 0, 1) for ey in (-1, 0, 1) for ez in (-1, 0, 1)
               if ex * ex + ey * ey + ez * ez < 3]

@@ -3,7 +3,7 @@
 Each test names the passage it checks.  None of them re-types the oracle's
 formulas: they use printed tables, exact moment identities, closed-form
 conservation increments, an independent stencil restatement of the step on
-periodic meshes, and the D3Q19 -> D2Q9 projection.
+periodic meshes, and the D3Q19 / D3Q27 -> D2Q9 projection.
 """
 import os
 from fractions import Fraction
@@ -58,6 +58,11 @@ def test_printed_d3q27_weights_fix_the_1d_weights():
         assert wt == expect[r[0]]
         total += wt * len(r[3:])
     assert total == 1
+    # the oracle's D3Q27 carries exactly these weights, class by |e|^2
+    e, w = O.lattice(27)
+    cls = {0: "rest", 1: "axis", 2: "edge", 3: "corner"}
+    for q in range(27):
+        assert w[q] == pytest.approx(float(expect[cls[int((e[q] ** 2).sum())]]), rel=1e-15)
     # and the oracle's D2Q9 weights are the 2-D products of the same rule
     e, w = O.lattice(9)
     for q in range(9):
@@ -65,7 +70,7 @@ def test_printed_d3q27_weights_fix_the_1d_weights():
         assert w[q] == pytest.approx(float(f[0] * f[1]), rel=1e-15)
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 27])
 def test_lattice_isotropy(lat):
     # Gauss-Hermite quadrature requirements for Eq. (icfeq): with c^2 = 3RT,
     # sum W = 1, sum W xi_a xi_b = RT delta_ab, sum W xi_a^4 = 3 RT^2,
@@ -94,9 +99,9 @@ def test_lattice_isotropy(lat):
 # --------------------------------------------------------------------------
 # equilibrium and force term (Eqs. icfeq, S)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 27])
 def test_feq_moments(lat):
-    d = cfg2(rho0=1.3, RT=0.7) if lat == 9 else cfg3(rho0=1.3, RT=0.7)
+    d = cfg2(rho0=1.3, RT=0.7) if lat == 9 else cfg3(rho0=1.3, RT=0.7, lattice=lat)
     e, _ = O.lattice(lat)
     D = 2 if lat == 9 else 3
     xi = np.sqrt(3 * 0.7) * e[:, :D]
@@ -110,11 +115,11 @@ def test_feq_moments(lat):
         np.testing.assert_allclose(P, rho * 0.7 * np.eye(D) + 1.3 * np.outer(u, u), rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 27])
 def test_force_term_moments(lat):
     # with the incompressible equilibrium: sum S = (rho0 - rho) G.u / RT,
     # sum xi S = rho G
-    d = cfg2(rho0=0.9, RT=0.4) if lat == 9 else cfg3(rho0=0.9, RT=0.4)
+    d = cfg2(rho0=0.9, RT=0.4) if lat == 9 else cfg3(rho0=0.9, RT=0.4, lattice=lat)
     e, _ = O.lattice(lat)
     D = 2 if lat == 9 else 3
     xi = np.sqrt(3 * 0.4) * e[:, :D]
@@ -151,7 +156,7 @@ def test_tanh_mesh_properties():
 # --------------------------------------------------------------------------
 # whole-step invariants
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 27])
 @pytest.mark.parametrize("stretch", [0, 1])
 def test_uniform_state_fixed_point(lat, stretch):
     # G = 0, periodic: any uniform equilibrium is preserved (coefficients sum
@@ -159,7 +164,7 @@ def test_uniform_state_fixed_point(lat, stretch):
     if lat == 9:
         d = cfg2(n=(6, 5), mesh=(stretch, stretch, 0), k_stretch=1.5)
     else:
-        d = cfg3(n=(4, 5, 3), mesh=(stretch,) * 3, k_stretch=1.5)
+        d = cfg3(n=(4, 5, 3), mesh=(stretch,) * 3, k_stretch=1.5, lattice=lat)
     D, Q, shp = O.dims(d)
     u = np.zeros((D,) + shp)
     u[0], u[1] = 0.04, -0.03
@@ -170,13 +175,13 @@ def test_uniform_state_fixed_point(lat, stretch):
     np.testing.assert_allclose(f1, f0, rtol=0, atol=2e-15)
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 27])
 @pytest.mark.parametrize("stretch", [0, 1])
 def test_periodic_conservation_without_force(lat, stretch):
     if lat == 9:
         d = cfg2(n=(7, 6), mesh=(stretch, stretch, 0), k_stretch=1.5)
     else:
-        d = cfg3(n=(4, 5, 6), mesh=(stretch,) * 3, k_stretch=1.5)
+        d = cfg3(n=(4, 5, 6), mesh=(stretch,) * 3, k_stretch=1.5, lattice=lat)
     D, Q, shp = O.dims(d)
     f0 = perturb(1, O.init(d, rho=1 + field(2, shp, 0.01), u=field(3, (D,) + shp, 0.05)), 1e-2)
     _, _, _, t0 = O.moments(d, f0)
@@ -184,12 +189,12 @@ def test_periodic_conservation_without_force(lat, stretch):
     np.testing.assert_allclose(t1[:4], t0[:4], rtol=0, atol=1e-12 * np.prod(shp))
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 27])
 def test_periodic_increments_with_force(lat):
     # Eq. (f_j+n) summed over velocities: per step and cell the momentum
     # grows by dt G (rho0 dt + 2 tau rho) / (2 tau + dt) and the mass by
     # 2 tau dt/(2 tau + dt) (rho0 - rho) G.u / RT (fluxes telescope)
-    d = cfg2(n=(6, 5), tau=0.3, dt=0.4) if lat == 9 else cfg3(n=(3, 4, 5), tau=0.3, dt=0.4)
+    d = cfg2(n=(6, 5), tau=0.3, dt=0.4) if lat == 9 else cfg3(n=(3, 4, 5), tau=0.3, dt=0.4, lattice=lat)
     D, Q, shp = O.dims(d)
     Gf = field(5, (D,) + shp, 1e-3)
     t = 0.7
@@ -222,7 +227,8 @@ def test_init_recovers_velocity():
 # --------------------------------------------------------------------------
 # independent restatement on periodic uniform meshes
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("lat,n,dx", [(9, (5, 4, 1), (0.5, 0.7)), (19, (3, 4, 5), (0.5, 0.6, 0.8))])
+@pytest.mark.parametrize("lat,n,dx", [(9, (5, 4, 1), (0.5, 0.7)), (19, (3, 4, 5), (0.5, 0.6, 0.8)),
+                                      (27, (3, 4, 5), (0.5, 0.6, 0.8))])
 def test_oracle_matches_stencil_restatement(lat, n, dx):
     D = 2 if lat == 9 else 3
     L = tuple(n[a] * dx[a] for a in range(D)) + ((1.0,) if D == 2 else ())
@@ -240,11 +246,12 @@ def test_oracle_matches_stencil_restatement(lat, n, dx):
 
 
 # --------------------------------------------------------------------------
-# D3Q19 projects onto D2Q9
+# D3Q19 and D3Q27 project onto D2Q9
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("lat3", [19, 27])
 @pytest.mark.parametrize("plane", [(0, 1), (0, 2), (1, 2)])
-def test_d3q19_reduces_to_d2q9(plane):
-    # summing D3Q19 over the velocity component normal to a plane gives the
+def test_3d_lattice_reduces_to_d2q9(lat3, plane):
+    # summing D3Q19 or D3Q27 over the velocity component normal to a plane gives the
     # D2Q9 weights; a flow invariant along that axis (periodic, no normal
     # velocity) therefore evolves exactly like the D2Q9 flow in the plane
     a, b = plane
@@ -267,10 +274,10 @@ def test_d3q19_reduces_to_d2q9(plane):
     uw3[2 * b + 1][a], uw3[2 * b + 1][b] = 0.05, 0.01
     G3 = [0.0] * 3
     G3[a] = 1e-4
-    d3 = dict(lattice=19, n=tuple(n3), L=tuple(L3), rho0=1.0, RT=1 / 3, tau=0.4, dt=0.5, bc=tuple(bc3),
+    d3 = dict(lattice=lat3, n=tuple(n3), L=tuple(L3), rho0=1.0, RT=1 / 3, tau=0.4, dt=0.5, bc=tuple(bc3),
               uw=uw3, G=tuple(G3))
     e2, _ = O.lattice(9)
-    e3, _ = O.lattice(19)
+    e3, _ = O.lattice(lat3)
 
     def to3(v2):  # 2-D field [.., 1, Y, X] -> 3-D [.., z, y, x], (X, Y) on axes (a, b), constant along c
         v = v2[..., 0, :, :]
@@ -282,12 +289,12 @@ def test_d3q19_reduces_to_d2q9(plane):
         return np.swapaxes(A, -1, -3)
 
     # 3-D initial state: split each 2-D population evenly over its e_c family
-    f3 = np.zeros((19, n3[2], n3[1], n3[0]))
+    f3 = np.zeros((lat3, n3[2], n3[1], n3[0]))
     fam = {}
-    for q3 in range(19):
+    for q3 in range(lat3):
         key = (e3[q3, a], e3[q3, b])
         fam.setdefault(key, []).append(q3)
-    _, w3 = O.lattice(19)
+    _, w3 = O.lattice(lat3)
     _, w2 = O.lattice(9)
     for q2 in range(9):
         key = (e2[q2, 0], e2[q2, 1])
