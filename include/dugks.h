@@ -20,6 +20,9 @@
  *   D3Q19 : ex outer, ey middle, ez inner, dropping the 8 corners
  *           |e|^2 = 3; rest state at q = 9, opposite of q is 18 - q;
  *           weights 1/3 (rest), 1/18 (|e|^2 = 1), 1/36 (|e|^2 = 2).
+ *   D3Q27 : the paper's 3-D set: ex outer, ey middle, ez inner, all 27;
+ *           rest state at q = 13, opposite of q is 26 - q; weights
+ *           products of 2/3 (component 0) and 1/6 (component +-1).
  *   Discrete velocities xi_q = sqrt(3 RT) e_q (Sec. II.C).
  * The stored state is f-tilde = f - dt/2 Omega - dt/2 S (Sec. II.B).
  *
@@ -59,7 +62,7 @@ extern "C" {
 #define DUGKS_ENONFINITE (-4)   /* moments found NaN/Inf in the state       */
 #define DUGKS_ENOMEM (-5)       /* device allocation of context tables      */
 
-enum dugks_lattice { DUGKS_D2Q9 = 9, DUGKS_D3Q19 = 19 };
+enum dugks_lattice { DUGKS_D2Q9 = 9, DUGKS_D3Q19 = 19, DUGKS_D3Q27 = 27 };
 enum dugks_dtype { DUGKS_F32 = 0, DUGKS_F64 = 1 };
 enum dugks_mesh_kind { DUGKS_UNIFORM = 0, DUGKS_TANH = 1 };
 /* equilibrium model: the paper's incompressible one (Eq. icfeq with

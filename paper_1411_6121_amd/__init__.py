@@ -8,7 +8,7 @@ fallback: without the built library every call raises.
 
 Configurations are plain dicts (keys as in ``dugks_config``)::
 
-    lattice 9|19, dtype "f32"|"f64", n (3), L (3), mesh (3), k_stretch,
+    lattice 9|19|27, dtype "f32"|"f64", n (3), L (3), mesh (3), k_stretch,
     rho0, RT, tau, dt, G (3), omega, phase, bc (6), uw (6x3), pw (6),
     model (0 incompressible, 1 original DUGKS equilibrium)
 

@@ -437,6 +437,7 @@ extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* f
     if (!f_n || !lam_np1 || !lam_n) return fail(ctx, DUGKS_EINVAL, "null buffer");
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE)
         return fail(ctx, DUGKS_EUNSUPPORTED, "the adjoint is derived for the incompressible model");
+    if (ctx->cfg.lattice == DUGKS_D3Q27) return fail(ctx, DUGKS_EUNSUPPORTED, "no D3Q27 adjoint");
     if (lam_n == f_n || lam_n == lam_np1) return fail(ctx, DUGKS_EINVAL, "lam_n must not alias f_n or lam_np1");
     for (int s = 0; s < 2 * ctx->D; ++s)
         if (ctx->cfg.bc[s] != DUGKS_PERIODIC)
@@ -457,6 +458,7 @@ extern "C" int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, 
     if (!lam0) return fail(ctx, DUGKS_EINVAL, "null adjoint state");
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE)
         return fail(ctx, DUGKS_EUNSUPPORTED, "the adjoint is derived for the incompressible model");
+    if (ctx->cfg.lattice == DUGKS_D3Q27) return fail(ctx, DUGKS_EUNSUPPORTED, "no D3Q27 adjoint");
     const hipStream_t st = (hipStream_t)stream;
     if (ctx->cfg.lattice == DUGKS_D2Q9) {
         if (ctx->cfg.dtype == DUGKS_F64) return init_vjp<D2Q9, double>(ctx, ctx->pd, u, force, t0, lam0, grad_u, grad_force, st);
@@ -473,6 +475,7 @@ extern "C" int dugks_moments_vjp(dugks_ctx* ctx, const void* grad_rho, const voi
     if (!lam) return fail(ctx, DUGKS_EINVAL, "null adjoint state");
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE)
         return fail(ctx, DUGKS_EUNSUPPORTED, "the adjoint is derived for the incompressible model");
+    if (ctx->cfg.lattice == DUGKS_D3Q27) return fail(ctx, DUGKS_EUNSUPPORTED, "no D3Q27 adjoint");
     const hipStream_t st = (hipStream_t)stream;
     if (ctx->cfg.lattice == DUGKS_D2Q9) {
         if (ctx->cfg.dtype == DUGKS_F64) return moments_vjp<D2Q9, double>(ctx, ctx->pd, grad_rho, grad_u, t, lam, grad_force, st);

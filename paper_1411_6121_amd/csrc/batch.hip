@@ -177,6 +177,7 @@ extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t
         if (offsets[i] < 0) return bfail(nullptr, DUGKS_EINVAL, "negative offset");
         if (cfgs[i].model != DUGKS_MODEL_INCOMPRESSIBLE)
             return bfail(nullptr, DUGKS_EUNSUPPORTED, "batched instances use the incompressible model");
+        if (cfgs[i].lattice == DUGKS_D3Q27) return bfail(nullptr, DUGKS_EUNSUPPORTED, "no batched D3Q27");
     }
     dugks_batch* b = new dugks_batch();
     b->n = n;

@@ -51,7 +51,10 @@ static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const dugks_config* c, std::string& why)
 {
     if (!c) { why = "null configuration"; return DUGKS_EINVAL; }
-    if (c->lattice != DUGKS_D2Q9 && c->lattice != DUGKS_D3Q19) { why = "lattice must be 9 or 19"; return DUGKS_EINVAL; }
+    if (c->lattice != DUGKS_D2Q9 && c->lattice != DUGKS_D3Q19 && c->lattice != DUGKS_D3Q27) {
+        why = "lattice must be 9, 19 or 27";
+        return DUGKS_EINVAL;
+    }
     if (c->dtype != DUGKS_F32 && c->dtype != DUGKS_F64) { why = "dtype must be F32 or F64"; return DUGKS_EINVAL; }
     const int D = c->lattice == DUGKS_D2Q9 ? 2 : 3;
     if (D == 2 && c->n[2] != 1) { why = "D2Q9 needs n[2] == 1"; return DUGKS_EINVAL; }
@@ -431,12 +434,15 @@ int launch_moments(dugks_ctx* ctx, const Inst<T>& P, const void* f, const void* 
 // ---------------------------------------------------------------------------
 // dispatch on (lattice, dtype)
 // ---------------------------------------------------------------------------
-#define DUGKS_DISPATCH(ctx, FN, ...)                                                        \
-    ((ctx)->cfg.lattice == DUGKS_D2Q9                                                       \
-         ? ((ctx)->cfg.dtype == DUGKS_F64 ? FN<D2Q9, double>((ctx), (ctx)->pd, __VA_ARGS__) \
-                                          : FN<D2Q9, float>((ctx), (ctx)->pf, __VA_ARGS__)) \
-         : ((ctx)->cfg.dtype == DUGKS_F64 ? FN<D3Q19, double>((ctx), (ctx)->pd, __VA_ARGS__) \
-                                          : FN<D3Q19, float>((ctx), (ctx)->pf, __VA_ARGS__)))
+#define DUGKS_DISPATCH(ctx, FN, ...)                                                          \
+    ((ctx)->cfg.lattice == DUGKS_D2Q9                                                         \
+         ? ((ctx)->cfg.dtype == DUGKS_F64 ? FN<D2Q9, double>((ctx), (ctx)->pd, __VA_ARGS__)   \
+                                          : FN<D2Q9, float>((ctx), (ctx)->pf, __VA_ARGS__))   \
+     : (ctx)->cfg.lattice == DUGKS_D3Q19                                                      \
+         ? ((ctx)->cfg.dtype == DUGKS_F64 ? FN<D3Q19, double>((ctx), (ctx)->pd, __VA_ARGS__)  \
+                                          : FN<D3Q19, float>((ctx), (ctx)->pf, __VA_ARGS__))  \
+         : ((ctx)->cfg.dtype == DUGKS_F64 ? FN<D3Q27, double>((ctx), (ctx)->pd, __VA_ARGS__)  \
+                                          : FN<D3Q27, float>((ctx), (ctx)->pf, __VA_ARGS__)))
 
 extern "C" int dugks_init(const dugks_config* cfg, const void* rho, const void* u, const void* force, void* f_out,
                           void* stream, dugks_ctx** out)

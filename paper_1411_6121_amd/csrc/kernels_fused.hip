@@ -661,6 +661,7 @@ int setup_fast(dugks_ctx* ctx)
 int resolve_step_kernel(const dugks_ctx* ctx, bool field)
 {
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) return 0;
+    if (ctx->cfg.lattice == DUGKS_D3Q27) return 0;
     if (ctx->fast != 4) return ctx->fast;
     const bool uni = ctx->cfg.dtype == DUGKS_F64 ? ctx->pd.uni != 0 : ctx->pf.uni != 0;
     return default_step_kernel(ctx->cfg.lattice, ctx->cfg.dtype, uni, field);
@@ -671,6 +672,7 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
     *handled = false;
     // the original-model variant runs on the general two-kernel path
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) return DUGKS_OK;
+    if (ctx->cfg.lattice == DUGKS_D3Q27) return DUGKS_OK;
     const int variant = resolve_step_kernel(ctx, force != nullptr);
     if (variant < 1 || variant > 3) return DUGKS_OK;
     *handled = true;

@@ -55,4 +55,20 @@ struct D3Q19 {
     }
 };
 
+// D3Q27: the paper's 3-D set (Sec. II.C), the full tensor product of the
+// three-point rule, e_x outer, e_y middle, e_z inner; rest at q = 13,
+// opp(q) = 26 - q; weights products of 2/3 (rest) and 1/6 (+-1).
+struct D3Q27 {
+    static constexpr int D = 3;
+    static constexpr int Q = 27;
+    static constexpr int REST = 13;
+    __host__ __device__ static constexpr int ex(int q) { return q / 9 - 1; }
+    __host__ __device__ static constexpr int ey(int q) { return (q / 3) % 3 - 1; }
+    __host__ __device__ static constexpr int ez(int q) { return q % 3 - 1; }
+    __host__ __device__ static constexpr int e(int q, int a) { return a == 0 ? ex(q) : a == 1 ? ey(q) : ez(q); }
+    __host__ __device__ static constexpr int opp(int q) { return Q - 1 - q; }
+    __host__ __device__ static constexpr double w1(int e) { return e == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+    __host__ __device__ static constexpr double w(int q) { return w1(ex(q)) * w1(ey(q)) * w1(ez(q)); }
+};
+
 }  // namespace dugks

@@ -58,7 +58,7 @@ def base_cfg(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(lattice=27), dict(n=(8, 8, 2)), dict(n=(0, 8, 1)), dict(tau=0.0), dict(dt=-1.0), dict(RT=float("nan")),
+    dict(lattice=15), dict(n=(8, 8, 2)), dict(n=(0, 8, 1)), dict(tau=0.0), dict(dt=-1.0), dict(RT=float("nan")),
     dict(bc=(1, 0, 0, 0, 0, 0)), dict(bc=(0, 0, 1, 1, 0, 0), n=(8, 1, 1)), dict(mesh=(1, 0, 0), k_stretch=0.0),
     dict(bc=(7, 7, 0, 0, 0, 0)), dict(L=(0.0, 8.0, 1.0)), dict(model=2),
 ])
