@@ -15,8 +15,8 @@ line:
              8 TB/s HBM peak; `traffic` = HBM bytes per launch measured with
              rocprofv3 counters (profiles/traffic.json), null when the kernel
              sources changed since
-  also       the same workload in FP32 and with the original-DUGKS
-             equilibrium; 64 uneven D2Q9 instances advanced by one batched
+  also       the same workload in FP32, with the original-DUGKS
+             equilibrium and on D3Q27; 64 uneven D2Q9 instances advanced by one batched
              launch per step (graph replay) vs 64 plain launches per step;
              the adjoint step vs the forward step (D2Q9 256^2 periodic, FP64)
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample
@@ -53,10 +53,11 @@ def cavity_cfg(n, dtype, mesh, re, lattice=19):
     uw = [[0.0] * 3 for _ in range(6)]
     uw[3] = [U, 0.0, 0.0]                       # lid: +y wall moving along +x
     tanh = 1 if mesh == "tanh" else 0
-    d = dict(lattice=lattice, dtype=dtype, n=(n, n, n if lattice == 19 else 1),
-             L=(float(n), float(n), float(n) if lattice == 19 else 1.0),
-             mesh=(tanh, tanh, tanh if lattice == 19 else 0), k_stretch=1.5, rho0=1.0, RT=RT, tau=nu / RT,
-             dt=1.0, bc=(1, 1, 1, 1, 1, 1) if lattice == 19 else (1, 1, 1, 1, 0, 0), uw=uw)
+    three = lattice != 9
+    d = dict(lattice=lattice, dtype=dtype, n=(n, n, n if three else 1),
+             L=(float(n), float(n), float(n) if three else 1.0),
+             mesh=(tanh, tanh, tanh if three else 0), k_stretch=1.5, rho0=1.0, RT=RT, tau=nu / RT,
+             dt=1.0, bc=(1, 1, 1, 1, 1, 1) if three else (1, 1, 1, 1, 0, 0), uw=uw)
     d["dt"] = M.dugks_dt_from_cfl(d, 0.5)
     return d
 
@@ -388,6 +389,17 @@ def main():
         also["original_model"] = {"ms_per_step": round(mso, 5), "mlups": round(cells / mso / 1e3, 2),
                                   "hbm_frac": round(bytes_per_step / (mso * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                   "kernel": "general (two launches)"}
+        # the paper's own 3-D velocity set on the same cavity
+        c27 = cavity_cfg(args.n, args.dtype, args.mesh, args.re, lattice=27)
+        f = torch.empty((27,) + shp, dtype=M.torch_dtype(c27), device="cuda")
+        g = torch.empty_like(f)
+        ctx = M.dugks_init(c27, f)
+        ms27, _ = time_steps(ctx, c27, f, g, max(args.steps // 4, 10), max(args.warmup // 4, 2))
+        M.dugks_destroy(ctx)
+        del f, g
+        b27 = 2.0 * 27 * esize * cells
+        also["d3q27"] = {"ms_per_step": round(ms27, 5), "mlups": round(cells / ms27 / 1e3, 2),
+                         "hbm_frac": round(b27 / (ms27 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         also["batched"] = bench_batched()
         also["adjoint"] = bench_adjoint()
         res["also"] = also

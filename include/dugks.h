@@ -93,6 +93,7 @@ enum dugks_bc {
  *   model       DUGKS_MODEL_INCOMPRESSIBLE (0, the paper's model) or
  *               DUGKS_MODEL_ORIGINAL (1: runs on the general kernels; no
  *               batched form, no adjoint: DUGKS_EUNSUPPORTED there)
+ * D3Q27 has no batched form and no adjoint (DUGKS_EUNSUPPORTED).
  */
 typedef struct {
     int lattice;
@@ -206,8 +207,9 @@ int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, 
  * interface evaluated by both neighbouring cells, 2 = fused single launch
  * with every interface evaluated once, 3 = as 2 with the velocity set split
  * over two lanes per column.  By default each launch takes the faster one
- * on MI355X: 3 for D2Q9, for D3Q19 FP64 without a force field and for
- * D3Q19 FP32 on uniform meshes without one; 2 otherwise.  A batch decides
+ * on MI355X: 3 for D2Q9 and D3Q27, for D3Q19 FP64 without a force field
+ * and for D3Q19 FP32 on uniform meshes without one; 2 otherwise.  The
+ * original-model variant always uses 0.  A batch decides
  * once for all its instances (uniform meshes, any force field), so batched
  * and single-instance states are bitwise equal when the instances share
  * the mesh kind and the presence of a force field.  All kernels give the

@@ -612,7 +612,8 @@ static int pick_chunk(const dugks_ctx* ctx, int variant)
     const int D = ctx->D;
     const int nM = ctx->cfg.n[D - 1];
     long tiles;
-    if (D == 3) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 11) / 12);
+    if (ctx->cfg.lattice == DUGKS_D3Q27) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 6) / 7);
+    else if (D == 3) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 11) / 12);
     else tiles = (ctx->cfg.n[0] + 125) / 126;
     // aim for >= 4 workgroups per CU on 256 CUs (the 512-thread FP64 D3Q19
     // split tiles run one per CU: >= 2.5), but march at least 8 planes
@@ -628,10 +629,11 @@ static int pick_chunk(const dugks_ctx* ctx, int variant)
 // tile and wins wherever its registers fit the occupancy it is built for;
 // with a force field its face-force interpolation spills (D3Q19 FP64), and
 // in FP32 only the uniform field-free instance fits four waves per SIMD, so
-// those cases take the one-lane kernel (2).  D2Q9: the split everywhere.
+// those cases take the one-lane kernel (2).  D2Q9 and D3Q27: the split
+// everywhere.
 int default_step_kernel(int lattice, int dtype, bool uniform, bool field)
 {
-    if (lattice == DUGKS_D2Q9) return 3;
+    if (lattice == DUGKS_D2Q9 || lattice == DUGKS_D3Q27) return 3;
     if (dtype == DUGKS_F64) return field ? 2 : 3;
     return (uniform && !field) ? 3 : 2;
 }
@@ -661,7 +663,8 @@ int setup_fast(dugks_ctx* ctx)
 int resolve_step_kernel(const dugks_ctx* ctx, bool field)
 {
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) return 0;
-    if (ctx->cfg.lattice == DUGKS_D3Q27) return 0;
+    // D3Q27 has the split kernel only (the one-lane tile would not fit a CU)
+    if (ctx->cfg.lattice == DUGKS_D3Q27) return ctx->fast == 0 ? 0 : 3;
     if (ctx->fast != 4) return ctx->fast;
     const bool uni = ctx->cfg.dtype == DUGKS_F64 ? ctx->pd.uni != 0 : ctx->pf.uni != 0;
     return default_step_kernel(ctx->cfg.lattice, ctx->cfg.dtype, uni, field);
@@ -672,7 +675,6 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
     *handled = false;
     // the original-model variant runs on the general two-kernel path
     if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) return DUGKS_OK;
-    if (ctx->cfg.lattice == DUGKS_D3Q27) return DUGKS_OK;
     const int variant = resolve_step_kernel(ctx, force != nullptr);
     if (variant < 1 || variant > 3) return DUGKS_OK;
     *handled = true;

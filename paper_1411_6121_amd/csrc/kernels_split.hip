@@ -678,7 +678,7 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
 {
     // FP32 D3Q19, uniform and field-free: fits four waves per SIMD (two
     // tiles per CU) without spills
-    constexpr int MINW_UF = (LAT::D == 3 && sizeof(T) == 4) ? 4 : MINW;
+    constexpr int MINW_UF = (LAT::Q == 19 && sizeof(T) == 4) ? 4 : MINW;
     if (P.uni) {
         if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true, true>(ctx, P, fin, fout, force, t, st, chunk);
         return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true>(ctx, P, fin, fout, force, t, st, chunk);
@@ -689,6 +689,12 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
 
 int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk)
 {
+    if (ctx->cfg.lattice == DUGKS_D3Q27) {
+        // 27 velocities: an 18 x 9 column tile keeps the LDS ring within a CU
+        if (ctx->cfg.dtype == DUGKS_F64)
+            return launch_split<D3Q27, double, 18, 9, 1, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+        return launch_split<D3Q27, float, 18, 9, 2, false>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+    }
     if (ctx->cfg.lattice == DUGKS_D3Q19) {
         if (ctx->cfg.dtype == DUGKS_F64)
             return launch_split<D3Q19, double, 18, 14, 1, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
