@@ -62,12 +62,19 @@ def cavity_cfg(n, dtype, mesh, re, lattice=19):
     return d
 
 
+# the sources the timed step kernels are compiled from, plus their launch
+# policy (tile, chunk and kernel choice) and the ABI header: the counters are
+# stale once any of these changes
+KERNEL_SOURCES = ("kernels_split.hip", "kernels_fused.hip", "march.hpp", "kernels_general.hpp", "inst.hpp",
+                  "lattice.hpp", "ctx.hpp", "../../include/dugks.h")
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1411_6121_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
+    for fn in KERNEL_SOURCES:
         with open(os.path.join(csrc, fn), "rb") as fh:
-            h.update(fn.encode())
+            h.update(os.path.basename(fn).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -183,6 +183,23 @@ int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, double t, vo
                   void* p, double* totals_host, void* stream);
 
 /*
+ * Convergence monitor of Sec. III (the steady criterion of the periodic
+ * flow, the periodic criterion of the Womersley flow): with u_a, u_b the
+ * velocities of Eq. (macro_values) of the states f_a at time t_a and f_b
+ * at time t_b (force field as in dugks_moments, nullable),
+ *   out_host[0] = sqrt(sum over cells |u_b - u_a|^2),
+ *   out_host[1] = sqrt(sum over cells |u_b|^2),
+ * unweighted sums as in the paper; the criterion is their ratio (for
+ * example below 1e-6 with t_b = t_a + 1000 dt).  The kinetic-energy
+ * history E_k = 1/2 int |u|^2 dx is totals[4] of dugks_moments.
+ * Deterministic reduction; uses the context's reduction scratch, so calls
+ * on one context must not overlap.  Synchronises the stream;
+ * DUGKS_ENONFINITE if either state holds a non-finite velocity.
+ */
+int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, const void* force, double t_a,
+                          double t_b, double* out_host, void* stream);
+
+/*
  * Reverse mode of one step on a fully periodic mesh (all sides
  * DUGKS_PERIODIC; other cases return DUGKS_EUNSUPPORTED):
  *   lam_n       = (d f_{n+1} / d f_n)^T lam_np1

@@ -87,6 +87,7 @@ def load():
     lib.dugks_step.argtypes = [_VP, _VP, _VP, _VP, D, _VP]
     lib.dugks_run.argtypes = [_VP, _VP, _VP, _VP, D, I, _VP, ctypes.POINTER(I)]
     lib.dugks_moments.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, ctypes.POINTER(D), _VP]
+    lib.dugks_velocity_change.argtypes = [_VP, _VP, _VP, _VP, D, D, ctypes.POINTER(D), _VP]
     lib.dugks_step_adjoint.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_init_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_moments_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP]
@@ -203,6 +204,16 @@ def dugks_moments(ctx, f, force=None, t=0.0, rho=None, u=None, p=None, totals=Tr
                               tot, _stream(stream))
     _check(rc, _VP(ctx))
     return list(tot) if totals else None
+
+
+def dugks_velocity_change(ctx, f_a, f_b, force=None, t_a=0.0, t_b=0.0, stream=None):
+    """(sqrt(sum |u_b - u_a|^2), sqrt(sum |u_b|^2)) over the cells for the
+    states f_a at t_a and f_b at t_b; their ratio is the steady/periodic
+    convergence criterion of Sec. III (synchronises)"""
+    out = (ctypes.c_double * 2)()
+    _check(load().dugks_velocity_change(_VP(ctx), _ptr(f_a), _ptr(f_b), _ptr(force), float(t_a), float(t_b), out,
+                                        _stream(stream)), _VP(ctx))
+    return out[0], out[1]
 
 
 def dugks_step_adjoint(ctx, f_n, lam_np1, lam_n, force=None, t_n=0.0, grad_force=None, stream=None):

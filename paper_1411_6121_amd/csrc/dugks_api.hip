@@ -359,6 +359,70 @@ __global__ __launch_bounds__(256) void k_moments_one(const Inst<T>* __restrict__
 }
 
 // fixed-order reduction of the per-block partials (deterministic)
+// velocity of cell ci of state f (Eq. macro_values) at time factor gt
+template <class LAT, typename T, bool ORIG>
+__device__ __forceinline__ void cell_velocity(const Inst<T>& P, const T* __restrict__ f, const T* __restrict__ force,
+                                              long long ci, T gt, T* u)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    T rho = T(0), j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const T v = f[(long long)q * P.nc + ci];
+        rho += v;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (LAT::e(q, a) == 1) j[a] += v;
+            if (LAT::e(q, a) == -1) j[a] -= v;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const T G = gt * (P.G0[a] + (force ? force[(long long)a * P.nc + ci] : T(0)));
+        u[a] = vel_from<T, ORIG>(P, rho, j[a], G, P.h);
+    }
+}
+
+// per-block partial sums of |u_b - u_a|^2 and |u_b|^2 (slots 0 and 1 of 6)
+template <class LAT, typename T, bool ORIG>
+__global__ __launch_bounds__(256) void k_velocity_change(const Inst<T>* __restrict__ Pp, const T* __restrict__ fa,
+                                                         const T* __restrict__ fb, const T* __restrict__ force, T gta,
+                                                         T gtb, double* partial)
+{
+    constexpr int D = LAT::D;
+    const Inst<T>& P = *Pp;
+    __shared__ double sh[2][256];
+    const long long ci = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0, b2 = 0.0;
+    if (ci < P.nc) {
+        T ua[3], ub[3];
+        cell_velocity<LAT, T, ORIG>(P, fa, force, ci, gta, ua);
+        cell_velocity<LAT, T, ORIG>(P, fb, force, ci, gtb, ub);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double du = (double)ub[a] - (double)ua[a];
+            d2 += du * du;
+            b2 += (double)ub[a] * (double)ub[a];
+        }
+    }
+    sh[0][threadIdx.x] = d2;
+    sh[1][threadIdx.x] = b2;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = partial + (long long)blockIdx.x * 6;
+        o[0] = sh[0][0];
+        o[1] = sh[1][0];
+        o[2] = o[3] = o[4] = o[5] = 0.0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_reduce6(const double* partial, int nblk, double* out)
 {
     __shared__ double sh[6][256];
@@ -427,6 +491,23 @@ int launch_moments(dugks_ctx* ctx, const Inst<T>& P, const void* f, const void* 
                            (const T*)f, (const T*)force, tfac(P, t), (T*)rho, (T*)u, (T*)p, ctx->partial);
     hipLaunchKernelGGL(k_reduce6, dim3(1), dim3(256), 0, st, (const double*)ctx->partial, (int)nb, ctx->totals_dev);
     return hip_check(ctx, hipGetLastError(), "moments launch");
+}
+
+template <class LAT, typename T>
+int launch_velocity_change(dugks_ctx* ctx, const Inst<T>& P, const void* fa, const void* fb, const void* force,
+                           double ta, double tb, hipStream_t st)
+{
+    const unsigned nb = nblocks(P.nc, 256);
+    if (P.orig)
+        hipLaunchKernelGGL((k_velocity_change<LAT, T, true>), dim3(nb), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)fa, (const T*)fb, (const T*)force, tfac(P, ta),
+                           tfac(P, tb), ctx->partial);
+    else
+        hipLaunchKernelGGL((k_velocity_change<LAT, T, false>), dim3(nb), dim3(256), 0, st,
+                           (const Inst<T>*)ctx->inst_dev, (const T*)fa, (const T*)fb, (const T*)force, tfac(P, ta),
+                           tfac(P, tb), ctx->partial);
+    hipLaunchKernelGGL(k_reduce6, dim3(1), dim3(256), 0, st, (const double*)ctx->partial, (int)nb, ctx->totals_dev);
+    return hip_check(ctx, hipGetLastError(), "velocity change launch");
 }
 
 }  // namespace dugks
@@ -579,6 +660,27 @@ extern "C" int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, d
         for (int m = 0; m < 6; ++m) totals_host[m] = tmp[m];
         if (tmp[5] != 0.0) return fail(ctx, DUGKS_ENONFINITE, "non-finite values in the state");
     }
+    return DUGKS_OK;
+}
+
+extern "C" int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, const void* force, double t_a,
+                                     double t_b, double* out_host, void* stream)
+{
+    if (!ctx) return fail(nullptr, DUGKS_EINVAL, "null context");
+    if (!f_a || !f_b || !out_host) return fail(ctx, DUGKS_EINVAL, "null buffer");
+    const hipStream_t st = (hipStream_t)stream;
+    int rc = DUGKS_DISPATCH(ctx, launch_velocity_change, f_a, f_b, force, t_a, t_b, st);
+    if (rc != DUGKS_OK) return rc;
+    double tmp[8];
+    rc = hip_check(ctx, hipMemcpyAsync(tmp, ctx->totals_dev, 6 * sizeof(double), hipMemcpyDeviceToHost, st),
+                   "monitor copy");
+    if (rc != DUGKS_OK) return rc;
+    rc = hip_check(ctx, hipStreamSynchronize(st), "monitor synchronise");
+    if (rc != DUGKS_OK) return rc;
+    out_host[0] = std::sqrt(tmp[0]);
+    out_host[1] = std::sqrt(tmp[1]);
+    if (!std::isfinite(out_host[0]) || !std::isfinite(out_host[1]))
+        return fail(ctx, DUGKS_ENONFINITE, "non-finite velocity in a state");
     return DUGKS_OK;
 }
 
