@@ -23,6 +23,7 @@ struct dugks_ctx {
     std::string err;
     int fast = 0;                 // fused-kernel variant selected at init (0 = none)
     int chunk = 0;                // planes marched per workgroup (0 = automatic)
+    int n_cu = 0;                 // compute units of the device the context was created on
     void* adj = nullptr;          // adjoint scratch (device, lazily)
     size_t adj_bytes = 0;
 };

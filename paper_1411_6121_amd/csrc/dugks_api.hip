@@ -535,6 +535,12 @@ extern "C" int dugks_init(const dugks_config* cfg, const void* rho, const void* 
     if (rc != DUGKS_OK) return fail(nullptr, rc, why);
     if (!f_out) return fail(nullptr, DUGKS_EINVAL, "null state buffer");
     dugks_ctx* ctx = new dugks_ctx();
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ctx->n_cu = 0;
+    }
     ctx->cfg = *cfg;
     ctx->D = cfg->lattice == DUGKS_D2Q9 ? 2 : 3;
     ctx->Q = cfg->lattice;

@@ -555,15 +555,18 @@ static int launch_fused(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     constexpr int D = LAT::D, M = D - 1;
     const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
-    const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = (size_t)3 * LAT::Q * BX * BY * sizeof(T);
     auto kern = k_fused<LAT, T, BX, BY, MINW>;
     static bool attr_set = false;
+    static long long slots = 0;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(ctx, e, "fused kernel LDS attribute");
+        slots = resident_slots(kern, BX * BY, lds, ctx->n_cu);
         attr_set = true;
     }
+    chunk = launch_chunk(chunk, (long long)tiles0 * tiles1, P.n[M], slots);
+    const int chunks = (P.n[M] + chunk - 1) / chunk;
     hipLaunchKernelGGL(kern, dim3(tiles0 * tiles1, chunks), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
                        (const T*)fin, (const T*)force, (T*)fout, t, chunk, tiles0);
     return hip_check(ctx, hipGetLastError(), "fused step launch");
@@ -576,15 +579,18 @@ static int launch_fused2_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, v
     constexpr int D = LAT::D, M = D - 1;
     const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
-    const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = fused2_lds<LAT, T, BX, BY>();
     auto kern = k_fused2<LAT, T, BX, BY, MINW, PF, FF, UNI>;
     static bool attr_set = false;
+    static long long slots = 0;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(ctx, e, "fused kernel LDS attribute");
+        slots = resident_slots(kern, BX * BY, lds, ctx->n_cu);
         attr_set = true;
     }
+    chunk = launch_chunk(chunk, (long long)tiles0 * tiles1, P.n[M], slots);
+    const int chunks = (P.n[M] + chunk - 1) / chunk;
     const long long nb = (long long)tiles0 * tiles1 * chunks;
     if (nb > 0x7fffffffLL) return fail(ctx, DUGKS_EUNSUPPORTED, "mesh too large for one launch");
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(BX * BY), lds, st, (const Inst<T>*)dev_inst(ctx),
@@ -602,26 +608,6 @@ static int launch_fused2(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void
     }
     if (force) return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, true, false>(ctx, P, fin, fout, force, t, st, chunk);
     return launch_fused2_ff<LAT, T, BX, BY, MINW, PF, false, false>(ctx, P, fin, fout, force, t, st, chunk);
-}
-
-// tile shapes: D3Q19 18x14 columns (16x12 interior), D2Q9 rows of 128
-// columns (126 interior); chunk = planes marched per workgroup
-static int pick_chunk(const dugks_ctx* ctx, int variant)
-{
-    if (ctx->chunk > 0) return std::min(ctx->chunk, std::max(ctx->cfg.n[ctx->D - 1], 1));
-    const int D = ctx->D;
-    const int nM = ctx->cfg.n[D - 1];
-    long tiles;
-    if (ctx->cfg.lattice == DUGKS_D3Q27) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 6) / 7);
-    else if (D == 3) tiles = (long)((ctx->cfg.n[0] + 15) / 16) * ((ctx->cfg.n[1] + 11) / 12);
-    else tiles = (ctx->cfg.n[0] + 125) / 126;
-    // aim for >= 4 workgroups per CU on 256 CUs (the 512-thread FP64 D3Q19
-    // split tiles run one per CU: >= 2.5), but march at least 8 planes
-    const long want = (variant == 3 && D == 3 && ctx->cfg.dtype == DUGKS_F64) ? 640 : 1024;
-    int chunk = 16;
-    while (chunk > 8 && tiles * ((nM + chunk - 1) / chunk) < want) chunk /= 2;
-    if (D == 2 && tiles * ((nM + chunk - 1) / chunk) < want) chunk = std::max(4, chunk / 2);
-    return std::min(chunk, std::max(nM, 1));
 }
 
 // Default step kernel (measured on MI355X, 128^3 D3Q19 and 1024^2 D2Q9
@@ -678,7 +664,9 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
     const int variant = resolve_step_kernel(ctx, force != nullptr);
     if (variant < 1 || variant > 3) return DUGKS_OK;
     *handled = true;
-    const int chunk = pick_chunk(ctx, variant);
+    // tiles: D3Q19 18 x 14 columns (16 x 12 interior), D2Q9 rows of 128
+    // columns (126 interior)
+    const int chunk = ctx->chunk;  // 0: chosen per launch (auto_chunk)
     if (variant == 3) return split_step(ctx, fin, fout, force, t, st, chunk);
     if (variant == 2) {
         if (ctx->cfg.lattice == DUGKS_D3Q19) {

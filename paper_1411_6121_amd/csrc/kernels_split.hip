@@ -322,7 +322,16 @@ __host__ __device__ constexpr int split_threads()
 
 // One workgroup's work: tile `tile` (of tiles0 x tiles1) and march chunk
 // `ck` of instance P; fin/fout/force point at the instance's arrays.
-template <class LAT, typename T, int BX, int BY, bool PF, bool UNI>
+// The cell's own f-tilde of Eq. (f_tilde_+) is kept in registers from the
+// plane load (OWN) instead of being read a second time, where the registers
+// allow it: D2Q9, and D3Q19 on uniform meshes without a force field.
+template <class LAT, typename T, bool UNI, bool FF>
+constexpr bool own_regs()
+{
+    return LAT::Q == 9 || (LAT::Q == 19 && UNI && !FF);
+}
+
+template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN>
 __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                            T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                            int ck, T* lds)
@@ -383,12 +392,25 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // element of (plane p, slot s, this column + (dx, dy))
     auto lds_el = [&](int p, int s, int dx, int dy) -> int { return ((ring(p) * Q + s) * BY + ty + dy) * BX + tx + dx; };
 
+    static_assert(!(PF && OWN), "the own-state registers assume no plane prefetch");
     T pf[K], prest = T(0), pg[3] = {T(0), T(0), T(0)};
+    // OWN: f-tilde of plane hi - 1 (the plane before the last one loaded)
+    T fo[K], fore = T(0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) pf[k] = fo[k] = T(0);
+    auto shift_own = [&]() {
+        if constexpr (OWN) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) fo[k] = pf[k];
+            fore = prest;
+        }
+    };
     auto plane_cell = [&](int p) -> long long {
         const int pp = perM ? ((p % nM) + nM) % nM : p;
         return int_idx(P, src[0], (D == 3) ? src[1] : pp, (D == 3) ? pp : 0);
     };
     auto load_plane = [&](int p) {
+        shift_own();
         if (cell_col) {
             const long long ci = plane_cell(p);
             const T* fp = fin + ci + q0off;
@@ -501,6 +523,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
             // are rewritten only after the barrier that ends this plane's
             // computation, by which time every wave has left that update.
             if (!computed(z + 1)) {
+                shift_own();
                 ghost_plane(z + 1, z, z - 1, P.rhi[M]);
             } else {
                 if (!PF) load_plane(z + 1);
@@ -520,6 +543,12 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         // the cell's own state for Eq. (f_tilde_+)
         T fz[K], fzr = T(0);
         auto load_own = [&]() {
+            if constexpr (OWN) {  // plane z = hi - 1
+#pragma unroll
+                for (int k = 0; k < K; ++k) fz[k] = fo[k];
+                fzr = fore;
+                return;
+            }
             const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
             const T* fp = fin + cidx + q0off;
 #pragma unroll
@@ -602,7 +631,8 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const Inst<T>& P = *Pp;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    split_body<LAT, T, BX, BY, PF, UNI>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, b % tiles, b / tiles,
+    split_body<LAT, T, BX, BY, PF, UNI, own_regs<LAT, T, UNI, FF>()>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk,
+                                                                    tiles0, b % tiles, b / tiles,
                                    reinterpret_cast<T*>(smem_raw));
 }
 
@@ -631,11 +661,13 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const T* force = (FF && forces && P.foff >= 0) ? forces + P.foff : nullptr;
     // per instance: the uniform-mesh body where every axis is uniform
     if (P.uni)
-        split_body<LAT, T, BX, BY, PF, true>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0,
-                                             local % ntile, local / ntile, reinterpret_cast<T*>(smem_raw));
+        split_body<LAT, T, BX, BY, PF, true, own_regs<LAT, T, true, FF>()>(
+            P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile, local / ntile,
+            reinterpret_cast<T*>(smem_raw));
     else
-        split_body<LAT, T, BX, BY, PF, false>(P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0,
-                                              local % ntile, local / ntile, reinterpret_cast<T*>(smem_raw));
+        split_body<LAT, T, BX, BY, PF, false, own_regs<LAT, T, false, FF>()>(
+            P, fin + P.off, force, fout + P.off, gt, gth, g.chunk, g.tiles0, local % ntile, local / ntile,
+            reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -655,15 +687,18 @@ static int launch_split_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, vo
     constexpr int D = LAT::D, M = D - 1;
     const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
-    const int chunks = (P.n[M] + chunk - 1) / chunk;
     const size_t lds = split_lds<LAT, T, BX, BY>();
     auto kern = k_split<LAT, T, BX, BY, MINW, PF, FF, UNI>;
     static bool attr_set = false;
+    static long long slots = 0;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_check(ctx, e, "split kernel LDS attribute");
+        slots = resident_slots(kern, split_threads<BX, BY>(), lds, ctx->n_cu);
         attr_set = true;
     }
+    chunk = launch_chunk(chunk, (long long)tiles0 * tiles1, P.n[M], slots);
+    const int chunks = (P.n[M] + chunk - 1) / chunk;
     const long long nb = (long long)tiles0 * tiles1 * chunks;
     if (nb > 0x7fffffffLL) return fail(ctx, DUGKS_EUNSUPPORTED, "mesh too large for one launch");
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(split_threads<BX, BY>()), lds, st,

@@ -37,6 +37,49 @@ __device__ __forceinline__ int xcd_order(int b, int nb)
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// Planes marched per workgroup (the chunk) of an automatic launch.  W(c) =
+// tiles * ceil(n / c) workgroups run in ceil(W / S) rounds on S resident
+// workgroups (CUs x workgroups per CU); a workgroup computes c + 2 planes of
+// f-bar-plus and c planes of faces and updates, about 2c + 2 plane stages of
+// similar cost.  The chunk minimises rounds x (2c + 2) over c = 1, 2, 4 ..
+// 32, the larger c on ties (fewer halo planes recomputed and re-read).
+// Small meshes thus march one or two planes per workgroup (the step is then
+// bound by the latency of one workgroup), large ones 8 to 16.
+inline int auto_chunk(long long tiles, int nM, long long slots)
+{
+    nM = nM > 1 ? nM : 1;
+    slots = slots > 1 ? slots : 1;
+    int best = 1;
+    double best_cost = 1e300;
+    for (int c = 1; c <= 32; c *= 2) {
+        const int cc = c < nM ? c : nM;
+        const long long W = tiles * ((nM + cc - 1) / cc);
+        const double cost = (double)((W + slots - 1) / slots) * (2.0 * cc + 2.0);
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = cc;
+        }
+        if (cc >= nM) break;
+    }
+    return best;
+}
+
+// workgroups of a step kernel resident on the whole device at once
+template <typename K>
+inline long long resident_slots(K kern, int threads, size_t lds, int n_cu)
+{
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, lds) != hipSuccess || per < 1) per = 1;
+    return (long long)per * (n_cu > 0 ? n_cu : 1);
+}
+
+// the chunk of a launch: the context's fixed value, else auto_chunk
+inline int launch_chunk(int fixed, long long tiles, int nM, long long slots)
+{
+    if (fixed > 0) return fixed < nM ? fixed : (nM > 1 ? nM : 1);
+    return auto_chunk(tiles, nM, slots);
+}
+
 // Occupancy bounds of a step kernel (waves per SIMD), for the attribute
 //   amdgpu_waves_per_eu(min, max).
 // The LDS ring decides how many workgroups share a CU; stating the true
