@@ -25,6 +25,7 @@ line:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
        [--mesh uniform|tanh] [--re 100] [--n 128] [--no-cpu-baseline]
        [--no-extras]
+       python bench.py --cavity-re12000   (the unsteady 2-D cavity of Sec. III)
        python bench.py --summarize-counters FETCH_DIR WRITE_DIR
          (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output of
           `bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras
@@ -288,6 +289,95 @@ def summarize_counters(fetch_dir, write_dir, workload):
     print(json.dumps(data[workload]))
 
 
+def cavity12000_cfg(n, dtype="f64"):
+    """Sec. III 2-D cavity at Re = 12000: L = 1, lid U = 1, RT = 100/3,
+    bounce-back walls, tanh mesh with k = 2.5, CFL 0.5, from rest"""
+    import paper_1411_6121_amd as M
+
+    U, RT, nu = 1.0, 100.0 / 3.0, 1.0 / 12000.0
+    uw = [[0.0] * 3 for _ in range(6)]
+    uw[3] = [U, 0.0, 0.0]
+    d = dict(lattice=9, dtype=dtype, n=(n, n, 1), L=(1.0, 1.0, 1.0), mesh=(1, 1, 0), k_stretch=2.5, rho0=1.0, RT=RT,
+             tau=nu / RT, dt=1.0, bc=(3, 3, 3, 3, 0, 0), uw=uw)
+    d["dt"] = M.dugks_dt_from_cfl(d, 0.5)
+    return d
+
+
+def main_frequency(t, ek):
+    """frequency of the largest spectral peak of E_k(t) above 0.05 (E_k
+    detrended by a quadratic fit, Hann window), and the resolution 1/T"""
+    import numpy as np
+
+    tc = t - t.mean()
+    e = ek - np.polyval(np.polyfit(tc, ek, 2), tc)
+    F = np.abs(np.fft.rfft(e * np.hanning(len(e)))) ** 2
+    fr = np.fft.rfftfreq(len(e), d=t[1] - t[0])
+    sel = fr > 0.05
+    return float(fr[sel][np.argmax(F[sel])]), float(1.0 / (t[-1] - t[0])), float(e.std() / ek.mean())
+
+
+def run_cavity12000(n, t_end, sample_dt=0.02):
+    """advance the Re = 12000 cavity from rest to t_end, E_k recorded on the
+    device every sample_dt (dugks_totals_async); reports the main frequency
+    of E_k over the second half and the steady criterion of Sec. III (relative
+    velocity change over the last 1000 steps)"""
+    import numpy as np
+    import torch
+
+    import paper_1411_6121_amd as M
+
+    d = cavity12000_cfg(n)
+    dt = d["dt"]
+    every = max(1, int(round(sample_dt / dt)))
+    nsamp = int(t_end / (every * dt))
+    fa = torch.empty((9, 1, n, n), dtype=torch.float64, device="cuda")
+    fb = torch.empty_like(fa)
+    hist = torch.zeros((nsamp, 6), dtype=torch.float64, device="cuda")
+    ctx = M.dugks_init(d, fa)
+    try:
+        cur, nxt = fa, fb
+        e0, e1 = _events()
+        e0.record()
+        last = time.time()
+        for s in range(nsamp):
+            if M.dugks_run(ctx, cur, nxt, every):
+                cur, nxt = nxt, cur
+            M.dugks_totals_async(ctx, cur, hist[s])
+            if time.time() - last > 20:
+                last = time.time()
+                print(f"[re12000 {n}^2] t = {(s + 1) * every * dt:.0f} of {t_end:g}", file=sys.stderr, flush=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prev = cur.clone()
+        if M.dugks_run(ctx, cur, nxt, 1000):
+            cur, nxt = nxt, cur
+        dn, bn = M.dugks_velocity_change(ctx, prev, cur)
+    finally:
+        M.dugks_destroy(ctx)
+    h = hist.cpu().numpy()
+    if h[:, 5].any():
+        raise RuntimeError("non-finite values during the Re = 12000 run")
+    t = (np.arange(nsamp) + 1) * every * dt
+    late = t > t_end / 2
+    f, res, osc = main_frequency(t[late], h[late, 4])
+    steps = nsamp * every
+    return {"n": n, "t_end": round(float(t[-1]), 2), "steps": steps, "dt": dt,
+            "ms_per_step": round(ms / steps, 5), "mlups": round(n * n * steps / (ms * 1e3), 1),
+            "ek_final": round(float(h[-1, 4]), 6), "ek_oscillation_rel": float(f"{osc:.3g}"),
+            "main_frequency": round(f, 4), "frequency_resolution": round(res, 4),
+            "velocity_change_1000_steps": float(f"{dn / bn:.3g}")}
+
+
+def bench_cavity12000(t_end128=3000.0, t_end_coarse=1500.0):
+    out = {"workload": "D2Q9 cavity Re 12000, tanh mesh k = 2.5, bounce-back walls, f64, from rest",
+           "paper": {"128": "periodic, main frequency 0.6144", "80, 96": "steady"}}
+    for n, te in ((128, t_end128), (96, t_end_coarse), (80, t_end_coarse)):
+        out[str(n)] = run_cavity12000(n, te)
+        print(f"[re12000 {n}^2] {json.dumps(out[str(n)])}", file=sys.stderr, flush=True)
+    return out
+
+
 def workload_name(n, mesh, re, dtype):
     return f"D3Q19 {n}^3 lid-driven cavity, {mesh}, Re {re:g}, NEQ walls, {dtype}"
 
@@ -306,6 +396,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--cavity-re12000", action="store_true",
+                    help="run the Re = 12000 2-D cavity (128^2 to t = 3000, 96^2 and 80^2 to t = 1500; "
+                         "about five minutes) and print its JSON line instead of the benchmark")
     args = ap.parse_args()
 
     workload = workload_name(args.n, args.mesh, args.re, args.dtype)
@@ -323,6 +416,9 @@ def main():
     import paper_1411_6121_amd as M
 
     torch.cuda.init()
+    if args.cavity_re12000:
+        print(json.dumps(bench_cavity12000()))
+        return
     cfg = cavity_cfg(args.n, args.dtype, args.mesh, args.re)
     Q, D, shp = M.shape_of(cfg)
     cells = int(shp[0] * shp[1] * shp[2])

@@ -183,6 +183,19 @@ int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, double t, vo
                   void* p, double* totals_host, void* stream);
 
 /*
+ * The six totals of dugks_moments (mass, momentum, kinetic energy E_k =
+ * 1/2 int |u|^2 dx, count of non-finite values) written to device memory
+ * totals_dev[0..5] (8-byte aligned, caller-owned) in stream order, without
+ * synchronising and without a host copy: calling it every k steps with
+ * successive slots records the E_k history of Sec. III on the device (and
+ * inside a captured graph).  Uses the context's reduction scratch: calls on
+ * one context go on one stream.  Non-finite values are reported in slot 5,
+ * not as an error.
+ */
+int dugks_totals_async(dugks_ctx* ctx, const void* f, const void* force, double t, double* totals_dev,
+                       void* stream);
+
+/*
  * Convergence monitor of Sec. III (the steady criterion of the periodic
  * flow, the periodic criterion of the Womersley flow): with u_a, u_b the
  * velocities of Eq. (macro_values) of the states f_a at time t_a and f_b

@@ -87,6 +87,7 @@ def load():
     lib.dugks_step.argtypes = [_VP, _VP, _VP, _VP, D, _VP]
     lib.dugks_run.argtypes = [_VP, _VP, _VP, _VP, D, I, _VP, ctypes.POINTER(I)]
     lib.dugks_moments.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, ctypes.POINTER(D), _VP]
+    lib.dugks_totals_async.argtypes = [_VP, _VP, _VP, D, _VP, _VP]
     lib.dugks_velocity_change.argtypes = [_VP, _VP, _VP, _VP, D, D, ctypes.POINTER(D), _VP]
     lib.dugks_step_adjoint.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_init_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
@@ -204,6 +205,13 @@ def dugks_moments(ctx, f, force=None, t=0.0, rho=None, u=None, p=None, totals=Tr
                               tot, _stream(stream))
     _check(rc, _VP(ctx))
     return list(tot) if totals else None
+
+
+def dugks_totals_async(ctx, f, out, force=None, t=0.0, stream=None):
+    """totals of dugks_moments into the device tensor `out` (6 float64
+    values, e.g. a row of a history buffer), in stream order, no sync"""
+    _check(load().dugks_totals_async(_VP(ctx), _ptr(f), _ptr(force), float(t), _ptr(out), _stream(stream)),
+           _VP(ctx))
 
 
 def dugks_velocity_change(ctx, f_a, f_b, force=None, t_a=0.0, t_b=0.0, stream=None):

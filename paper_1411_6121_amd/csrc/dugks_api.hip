@@ -480,7 +480,7 @@ int launch_init(dugks_ctx* ctx, const Inst<T>& P, const void* rho, const void* u
 
 template <class LAT, typename T>
 int launch_moments(dugks_ctx* ctx, const Inst<T>& P, const void* f, const void* force, double t, void* rho,
-                   void* u, void* p, hipStream_t st)
+                   void* u, void* p, double* totals, hipStream_t st)
 {
     const unsigned nb = nblocks(P.nc, 256);
     if (P.orig)
@@ -489,7 +489,7 @@ int launch_moments(dugks_ctx* ctx, const Inst<T>& P, const void* f, const void* 
     else
         hipLaunchKernelGGL((k_moments_one<LAT, T, false>), dim3(nb), dim3(256), 0, st, (const Inst<T>*)ctx->inst_dev,
                            (const T*)f, (const T*)force, tfac(P, t), (T*)rho, (T*)u, (T*)p, ctx->partial);
-    hipLaunchKernelGGL(k_reduce6, dim3(1), dim3(256), 0, st, (const double*)ctx->partial, (int)nb, ctx->totals_dev);
+    hipLaunchKernelGGL(k_reduce6, dim3(1), dim3(256), 0, st, (const double*)ctx->partial, (int)nb, totals);
     return hip_check(ctx, hipGetLastError(), "moments launch");
 }
 
@@ -654,7 +654,7 @@ extern "C" int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, d
     if (!ctx) return fail(nullptr, DUGKS_EINVAL, "null context");
     if (!f) return fail(ctx, DUGKS_EINVAL, "null state buffer");
     const hipStream_t st = (hipStream_t)stream;
-    int rc = DUGKS_DISPATCH(ctx, launch_moments, f, force, t, rho, u, p, st);
+    int rc = DUGKS_DISPATCH(ctx, launch_moments, f, force, t, rho, u, p, ctx->totals_dev, st);
     if (rc != DUGKS_OK) return rc;
     if (totals_host) {
         double tmp[8];
@@ -667,6 +667,14 @@ extern "C" int dugks_moments(dugks_ctx* ctx, const void* f, const void* force, d
         if (tmp[5] != 0.0) return fail(ctx, DUGKS_ENONFINITE, "non-finite values in the state");
     }
     return DUGKS_OK;
+}
+
+extern "C" int dugks_totals_async(dugks_ctx* ctx, const void* f, const void* force, double t, double* totals_dev,
+                                  void* stream)
+{
+    if (!ctx) return fail(nullptr, DUGKS_EINVAL, "null context");
+    if (!f || !totals_dev) return fail(ctx, DUGKS_EINVAL, "null buffer");
+    return DUGKS_DISPATCH(ctx, launch_moments, f, force, t, nullptr, nullptr, nullptr, totals_dev, (hipStream_t)stream);
 }
 
 extern "C" int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, const void* force, double t_a,

@@ -1,6 +1,7 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times: the D3Q19 128^3 cavity (uniform and tanh meshes, FP64 and
-FP32), the D2Q9 1024^2 cavity, and the 64-instance uneven batch.
+FP32), the D2Q9 1024^2 cavity, the 2-D Re = 12000 cavity (128^2 tanh
+mesh, bounce-back walls) and the 64-instance uneven batch.
 
 Whole-field comparisons: one oracle step at these sizes takes well under a
 second on the host cores, so every output value is checked, not a sample.
@@ -79,6 +80,19 @@ def test_cavity_1024_d2q9_f64():
     f0 = flow_state(oc, 63)
     ref = O.run(oc, f0, 2)
     got = gpu_steps(cfg, f0, 2)
+    assert rel_linf(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [128, 80])
+def test_cavity_re12000_f64(n):
+    cfg = bench.cavity12000_cfg(n)
+    say(f"[full size] D2Q9 {n}^2 Re 12000 cavity, tanh k=2.5, bounce-back, f64")
+    oc = {k: v for k, v in cfg.items() if k != "dtype"}
+    # a lid-scale velocity field so that every term (and the walls) is active
+    Q, D, shp = M.shape_of(cfg)
+    f0 = perturb(66, O.init(oc, rho=1.0 + field(64, shp, 1e-3), u=field(65, (D,) + shp, 0.3)), 1e-3)
+    ref = O.run(oc, f0, 3)
+    got = gpu_steps(cfg, f0, 3)
     assert rel_linf(got, ref) < 1e-12
 
 

@@ -110,3 +110,26 @@ def test_channel_converges_to_poiseuille_under_the_steady_criterion():
     say(f"[monitor] steady after {blocks} blocks")
     err = np.sqrt(((ux - ua) ** 2).sum() / (ua ** 2).sum())
     assert err < 2e-3
+
+
+def test_totals_async_equals_moments_totals():
+    cfg = CASES[0]
+    force = case_force(cfg, 5)
+    f = to_dev(start_state(cfg, 23, force), cfg)
+    fr = to_dev(force, cfg)
+    hist = torch.full((3, 6), -1.0, dtype=torch.float64, device="cuda")
+    ctx = M.dugks_init(cfg, torch.empty_like(f))
+    try:
+        M.dugks_totals_async(ctx, f, hist[1], fr, 0.25)
+        torch.cuda.synchronize()
+        ref = M.dugks_moments(ctx, f, fr, 0.25)
+        bad = f.clone()
+        bad[2, 0, 1, 1] = float("inf")
+        M.dugks_totals_async(ctx, bad, hist[2], fr, 0.25)
+        torch.cuda.synchronize()
+    finally:
+        M.dugks_destroy(ctx)
+    h = hist.cpu().numpy()
+    assert (h[0] == -1.0).all()                 # untouched neighbour row
+    assert np.array_equal(h[1], np.asarray(ref))  # same reduction, bitwise
+    assert h[2, 5] == 1.0                       # non-finite count, no error
