@@ -761,17 +761,146 @@ static void feq_partials(const octx* o, const oracle_cfg* cfg, int q, double rho
 
 static inline int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
+/* Step 3 (cross points) and step 4 for one face value: F(x_b) for velocity
+ * q on the face of axis a with coordinates c (c[a] = face index), written
+ * out as in the forward step; the reverse scatter below is its transpose. */
+static double face_value(const octx* o, const double* fp, int a, const int* c, int q, double h)
+{
+    const int D = o->D, Q = o->Q;
+    int cl[3] = {c[0], c[1], c[2]};
+    cl[a] -= 1;
+    const double w = o->w[a][c[a]], gn = o->g[a][c[a]];
+    const long L = cell_ext(o, cl[0], cl[1], cl[2]), R = cell_ext(o, c[0], c[1], c[2]);
+    double sig[3] = {0, 0, 0};
+    sig[a] = gn * (fp[R * Q + q] - fp[L * Q + q]);
+    for (int b = 0; b < D; ++b) {
+        if (b == a) continue;
+        double ev[2];
+        for (int up = 0; up < 2; ++up) {
+            int ce_[3] = {c[0], c[1], c[2]};
+            ce_[b] += up;
+            const double wa = o->w[a][ce_[a]], wb = o->w[b][ce_[b]];
+            int c00[3] = {ce_[0], ce_[1], ce_[2]}, c10[3] = {ce_[0], ce_[1], ce_[2]};
+            int c01[3] = {ce_[0], ce_[1], ce_[2]}, c11[3] = {ce_[0], ce_[1], ce_[2]};
+            c00[a] -= 1; c00[b] -= 1; c10[b] -= 1; c01[a] -= 1;
+            const double e1 = (1.0 - wa) * fp[cell_ext(o, c00[0], c00[1], c00[2]) * Q + q] +
+                              wa * fp[cell_ext(o, c10[0], c10[1], c10[2]) * Q + q];
+            const double e2 = (1.0 - wa) * fp[cell_ext(o, c01[0], c01[1], c01[2]) * Q + q] +
+                              wa * fp[cell_ext(o, c11[0], c11[1], c11[2]) * Q + q];
+            ev[up] = (1.0 - wb) * e1 + wb * e2;
+        }
+        sig[b] = (ev[1] - ev[0]) / o->dl[b][c[b]];
+    }
+    double xs = 0.0;
+    for (int b = 0; b < D; ++b) xs += o->xi[q][b] * sig[b];
+    return (1.0 - w) * fp[L * Q + q] + w * fp[R * Q + q] - h * xs;
+}
+
+/* transpose of face_value: fpb += Fq * dF/dfp */
+static void face_value_adj(const octx* o, double* fpb, int a, const int* c, int q, double h, double Fq)
+{
+    const int D = o->D, Q = o->Q;
+    int cl[3] = {c[0], c[1], c[2]};
+    cl[a] -= 1;
+    const double w = o->w[a][c[a]], gn = o->g[a][c[a]];
+    const long L = cell_ext(o, cl[0], cl[1], cl[2]), R = cell_ext(o, c[0], c[1], c[2]);
+    fpb[L * Q + q] += (1.0 - w) * Fq;
+    fpb[R * Q + q] += w * Fq;
+    const double sa = -h * o->xi[q][a] * Fq;
+    fpb[R * Q + q] += gn * sa;
+    fpb[L * Q + q] -= gn * sa;
+    for (int b = 0; b < D; ++b) {
+        if (b == a) continue;
+        const double sb = -h * o->xi[q][b] * Fq / o->dl[b][c[b]];
+        for (int up = 0; up < 2; ++up) {
+            const double sgn = up ? sb : -sb;
+            int ce_[3] = {c[0], c[1], c[2]};
+            ce_[b] += up;
+            const double wa = o->w[a][ce_[a]], wb = o->w[b][ce_[b]];
+            int c00[3] = {ce_[0], ce_[1], ce_[2]}, c10[3] = {ce_[0], ce_[1], ce_[2]};
+            int c01[3] = {ce_[0], ce_[1], ce_[2]}, c11[3] = {ce_[0], ce_[1], ce_[2]};
+            c00[a] -= 1; c00[b] -= 1; c10[b] -= 1; c01[a] -= 1;
+            fpb[cell_ext(o, c00[0], c00[1], c00[2]) * Q + q] += (1.0 - wb) * (1.0 - wa) * sgn;
+            fpb[cell_ext(o, c10[0], c10[1], c10[2]) * Q + q] += (1.0 - wb) * wa * sgn;
+            fpb[cell_ext(o, c01[0], c01[1], c01[2]) * Q + q] += wb * (1.0 - wa) * sgn;
+            fpb[cell_ext(o, c11[0], c11[1], c11[2]) * Q + q] += wb * wa * sgn;
+        }
+    }
+}
+
+/* transpose of ghost_fill: fold the adjoint of every ghost point back into
+ * the points it was made from, axes in the reverse of the forward order */
+static void ghost_fold(const octx* o, double* v, int ncomp)
+{
+    for (int a = o->D - 1; a >= 0; --a) {
+        int lo[3], hi[3];
+        for (int b = 0; b < 3; ++b) {
+            if (b >= o->D) { lo[b] = 0; hi[b] = 0; continue; }
+            if (b < a) { lo[b] = -1; hi[b] = o->n[b]; }
+            else { lo[b] = 0; hi[b] = o->n[b] - 1; }
+        }
+        const int N = o->n[a];
+        for (int side = 0; side < 2; ++side) {
+            lo[a] = hi[a] = side ? N : -1;
+            for (int k = lo[2]; k <= hi[2]; ++k)
+                for (int j = lo[1]; j <= hi[1]; ++j)
+                    for (int i = lo[0]; i <= hi[0]; ++i) {
+                        int c0[3] = {i, j, k}, c1[3] = {i, j, k};
+                        const long dst = cell_ext(o, i, j, k);
+                        if (o->per[a]) {
+                            c0[a] = side ? 0 : N - 1;
+                            const long src = cell_ext(o, c0[0], c0[1], c0[2]);
+                            for (int m = 0; m < ncomp; ++m) v[src * ncomp + m] += v[dst * ncomp + m];
+                        } else {
+                            const double r = side ? o->rhi[a] : o->rlo[a];
+                            c0[a] = side ? N - 1 : 0;
+                            c1[a] = side ? N - 2 : 1;
+                            const long s0 = cell_ext(o, c0[0], c0[1], c0[2]);
+                            const long s1 = cell_ext(o, c1[0], c1[1], c1[2]);
+                            for (int m = 0; m < ncomp; ++m) {
+                                v[s0 * ncomp + m] += (1.0 - r) * v[dst * ncomp + m];
+                                v[s1 * ncomp + m] += r * v[dst * ncomp + m];
+                            }
+                        }
+                        for (int m = 0; m < ncomp; ++m) v[dst * ncomp + m] = 0.0;
+                    }
+        }
+    }
+}
+
+/* moments of a face value set at time factor gth (steps 6, model 0) */
+static void face_macro(const octx* o, const oracle_cfg* cfg, const double* Fb, const double* G, double h,
+                       double* rho, double* u)
+{
+    double r = 0.0, m[3] = {0, 0, 0};
+    for (int q = 0; q < o->Q; ++q) {
+        r += Fb[q];
+        for (int b = 0; b < o->D; ++b) m[b] += o->xi[q][b] * Fb[q];
+    }
+    *rho = r;
+    for (int b = 0; b < 3; ++b) u[b] = 0.0;
+    for (int b = 0; b < o->D; ++b) u[b] = (m[b] + cfg->rho0 * G[b] * h / 2.0) / cfg->rho0;
+}
+
+/* Reverse mode of one step (incompressible model) on any mesh and boundary
+ * set: the forward intermediates are recomputed (no tape), then every step
+ * of the forward is transposed in reverse order: the update (steps 8-9),
+ * the original distribution at the faces (step 7 with the step-6 moments),
+ * the wall rules (step 5: bounce-back is a permutation plus a constant; the
+ * NEQ rules depend on the moments and values of the opposite interface of
+ * the wall cell), the reconstruction (steps 3-4), the ghost points (step 2)
+ * and Eq. (f_bar_+) with the macroscopic recovery (step 1).  Face n of a
+ * periodic axis is computed by the forward step as a face of its own (equal
+ * to face 0), and is transposed as one. */
 int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* force, double t,
                         const double* lam, double* lam_out, double* grad_force)
 {
     octx o;
     if (cfg->model != 0) return -2; /* derived for the incompressible model */
     if (setup(&o, cfg)) return -1;
-    for (int a = 0; a < o.D; ++a)
-        if (!o.per[a]) { ctx_free(&o); return -2; }
     const int D = o.D, Q = o.Q;
     const long nc = ncells(&o), nce = ncells_ext(&o);
-    const double dt = cfg->dt, h = 0.5 * dt, tau = cfg->tau, rho0 = cfg->rho0;
+    const double dt = cfg->dt, h = 0.5 * dt, tau = cfg->tau, rho0 = cfg->rho0, RT = cfg->RT;
     const double A1 = (2.0 * tau - h) / (2.0 * tau + dt);
     const double B1 = 3.0 * h / (2.0 * tau + dt);
     const double C1 = 3.0 * tau * h / (2.0 * tau + dt);
@@ -780,7 +909,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
     const double C7 = tau * h / (2.0 * tau + h);
     const double gt = gtime(cfg, t), gth = gtime(cfg, t + h);
 
-    /* ---- forward recomputation of steps 1-4 and the face moments ---- */
+    /* ---- forward recomputation: step 1, step 2, steps 3-4, step 5 ---- */
     double* Gext = force_ext(&o, force);
     double* fp = (double*)calloc((size_t)nce * Q, sizeof(double));
     double* rho_c = (double*)calloc((size_t)nc, sizeof(double));
@@ -806,55 +935,78 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
             }
     ghost_fill(&o, fp, Q);
 
-    /* per face: F after step 4 (values before step 7) */
-    double* F[3] = {NULL, NULL, NULL};
+    /* F4: face values after step 4; F5: after the wall rules of step 5 */
+    double* F4[3] = {NULL, NULL, NULL};
+    double* F5[3] = {NULL, NULL, NULL};
+    double* Fb5[3] = {NULL, NULL, NULL}; /* adjoint of F5, then of F4 */
+    double* Gbf[3] = {NULL, NULL, NULL}; /* adjoint of the face acceleration */
     for (int a = 0; a < D; ++a) {
         long nf = face_count(&o, a);
-        F[a] = (double*)malloc(sizeof(double) * nf * Q);
+        F4[a] = (double*)malloc(sizeof(double) * nf * Q);
+        F5[a] = (double*)malloc(sizeof(double) * nf * Q);
+        Fb5[a] = (double*)calloc((size_t)nf * Q, sizeof(double));
+        Gbf[a] = (double*)calloc((size_t)nf * 3, sizeof(double));
         int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
         for (int k = 0; k < d2; ++k)
             for (int j = 0; j < d1; ++j)
                 for (int i = 0; i < d0; ++i) {
-                    int c[3] = {i, j, k}, cl[3] = {i, j, k};
-                    cl[a] -= 1;
-                    double w = o.w[a][c[a]], gn = o.g[a][c[a]];
-                    long L = cell_ext(&o, cl[0], cl[1], cl[2]), R = cell_ext(&o, c[0], c[1], c[2]);
+                    int c[3] = {i, j, k};
                     long fi = face_idx(&o, a, c);
                     for (int q = 0; q < Q; ++q) {
-                        double sig[3] = {0, 0, 0};
-                        sig[a] = gn * (fp[R * Q + q] - fp[L * Q + q]);
-                        for (int b = 0; b < D; ++b) {
-                            if (b == a) continue;
-                            /* the two cross points of this face along b */
-                            double ev[2];
-                            for (int up = 0; up < 2; ++up) {
-                                int ce_[3] = {i, j, k};
-                                ce_[b] += up;
-                                double wa = o.w[a][ce_[a]], wb = o.w[b][ce_[b]];
-                                int c00[3] = {ce_[0], ce_[1], ce_[2]}, c10[3] = {ce_[0], ce_[1], ce_[2]};
-                                int c01[3] = {ce_[0], ce_[1], ce_[2]}, c11[3] = {ce_[0], ce_[1], ce_[2]};
-                                c00[a] -= 1; c00[b] -= 1; c10[b] -= 1; c01[a] -= 1;
-                                double e1 = (1.0 - wa) * fp[cell_ext(&o, c00[0], c00[1], c00[2]) * Q + q] +
-                                            wa * fp[cell_ext(&o, c10[0], c10[1], c10[2]) * Q + q];
-                                double e2 = (1.0 - wa) * fp[cell_ext(&o, c01[0], c01[1], c01[2]) * Q + q] +
-                                            wa * fp[cell_ext(&o, c11[0], c11[1], c11[2]) * Q + q];
-                                ev[up] = (1.0 - wb) * e1 + wb * e2;
-                            }
-                            sig[b] = (ev[1] - ev[0]) / o.dl[b][c[b]];
+                        F4[a][fi * Q + q] = face_value(&o, fp, a, c, q, h);
+                        F5[a][fi * Q + q] = F4[a][fi * Q + q];
+                    }
+                }
+    }
+    for (int s = 0; s < 2 * D; ++s) {
+        int a = s / 2, hi = s % 2;
+        if (o.per[a]) continue;
+        int bc = cfg->bc[s], N = o.n[a];
+        int nsg = hi ? 1 : -1;
+        int lo[3] = {0, 0, 0}, up[3];
+        for (int b = 0; b < 3; ++b) up[b] = o.n[b] - 1;
+        lo[a] = up[a] = 0;
+        for (int k = lo[2]; k <= up[2]; ++k)
+            for (int j = lo[1]; j <= up[1]; ++j)
+                for (int i = lo[0]; i <= up[0]; ++i) {
+                    int cw[3] = {i, j, k}, co[3] = {i, j, k};
+                    cw[a] = hi ? N : 0;
+                    co[a] = hi ? N - 1 : 1;
+                    const double* Pw = F4[a] + face_idx(&o, a, cw) * Q;
+                    double* Fw = F5[a] + face_idx(&o, a, cw) * Q;
+                    const double* Fo = F4[a] + face_idx(&o, a, co) * Q;
+                    if (bc == OR_BOUNCE_BACK) {
+                        for (int q = 0; q < Q; ++q) {
+                            if (o.e[q][a] * nsg >= 0) continue;
+                            double xu = 0.0;
+                            for (int b = 0; b < D; ++b) xu += o.xi[q][b] * cfg->uw[s][b];
+                            Fw[q] = Pw[o.opp[q]] + 2.0 * rho0 * o.W[q] * xu / RT;
                         }
-                        double xs = 0.0;
-                        for (int b = 0; b < D; ++b) xs += o.xi[q][b] * sig[b];
-                        F[a][fi * Q + q] = (1.0 - w) * fp[L * Q + q] + w * fp[R * Q + q] - h * xs;
+                    } else {
+                        double rc, uc[3], Gb[3], ra, ua[3] = {0, 0, 0};
+                        accel_face(&o, cfg, Gext, a, co, gth, Gb);
+                        face_macro(&o, cfg, Fo, Gb, h, &rc, uc);
+                        if (bc == OR_NEQ_VELOCITY) {
+                            ra = rc;
+                            for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
+                        } else {
+                            ra = rho0 + cfg->pw[s] / RT;
+                            for (int b = 0; b < D; ++b) ua[b] = uc[b];
+                        }
+                        for (int q = 0; q < Q; ++q) {
+                            if (o.e[q][a] * nsg >= 0) continue;
+                            Fw[q] = feq_q(&o, cfg, q, ra, ua) + (Fo[q] - feq_q(&o, cfg, q, rc, uc));
+                        }
                     }
                 }
     }
 
     /* ---- reverse sweep ---- */
-    double* fpb = (double*)calloc((size_t)nce * Q, sizeof(double)); /* adjoint of f-bar-plus (ext) */
-    double* Gb_sp = (double*)calloc((size_t)nce * 3, sizeof(double)); /* adjoint of spatial force (ext) */
+    double* fpb = (double*)calloc((size_t)nce * Q, sizeof(double));  /* adjoint of f-bar-plus (ext) */
+    double* Gb_sp = (double*)calloc((size_t)nce * 3, sizeof(double)); /* adjoint of the spatial force (ext) */
     for (long c = 0; c < nc * Q; ++c) lam_out[c] = 0.0;
 
-    /* steps 8-9: f~new = 4/3 fp - 1/3 f~ - dt/V sum (xi.n) Fo s */
+    /* steps 8-9: f~new = 4/3 f-bar-plus - 1/3 f~ - dt/V sum_faces (xi.n) F s */
     for (int k = 0; k < o.n[2]; ++k)
         for (int j = 0; j < o.n[1]; ++j)
             for (int i = 0; i < o.n[0]; ++i) {
@@ -864,7 +1016,8 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                     lam_out[q * nc + ci] += -1.0 / 3.0 * lam[q * nc + ci];
                 }
             }
-    /* adjoint of each face value Fo (face n of a periodic axis is face 0) */
+
+    /* step 7 at every face, from the flux adjoint of its (at most two) cells */
     for (int a = 0; a < D; ++a) {
         int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
         int N = o.n[a];
@@ -872,120 +1025,145 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
             for (int j = 0; j < d1; ++j)
                 for (int i = 0; i < d0; ++i) {
                     int c[3] = {i, j, k};
-                    if (c[a] == N) continue; /* alias of face 0 */
                     long fi = face_idx(&o, a, c);
-                    /* cells on the two sides: left (+ face of it), right (- face) */
-                    int cl[3] = {i, j, k}, cr[3] = {i, j, k};
-                    cl[a] = wrapi(c[a] - 1, N);
-                    cr[a] = c[a];
-                    long li = cell_int(&o, cl[0], cl[1], cl[2]), ri = cell_int(&o, cr[0], cr[1], cr[2]);
-                    double Vl = 1.0, Vr = 1.0, sl = 1.0, sr = 1.0;
-                    for (int b = 0; b < D; ++b) {
-                        Vl *= o.dl[b][cl[b]];
-                        Vr *= o.dl[b][cr[b]];
-                        if (b != a) { sl *= o.dl[b][cl[b]]; sr *= o.dl[b][cr[b]]; }
-                    }
                     double Fo_b[MAXQ];
-                    for (int q = 0; q < Q; ++q)
-                        Fo_b[q] = -dt / Vl * o.xi[q][a] * sl * lam[q * nc + li] +
-                                  dt / Vr * o.xi[q][a] * sr * lam[q * nc + ri];
-                    /* recompute face moments */
-                    const double* Fb = F[a] + fi * Q;
-                    double rho = 0.0, m[3] = {0, 0, 0}, G[3], u[3] = {0, 0, 0};
-                    for (int q = 0; q < Q; ++q) {
-                        rho += Fb[q];
-                        for (int b = 0; b < D; ++b) m[b] += o.xi[q][b] * Fb[q];
+                    for (int q = 0; q < Q; ++q) Fo_b[q] = 0.0;
+                    for (int side = 0; side < 2; ++side) {
+                        int cc[3] = {i, j, k};
+                        cc[a] = side ? c[a] : c[a] - 1; /* side 0: the cell below (this is its + face) */
+                        if (cc[a] < 0 || cc[a] >= N) continue;
+                        double V = 1.0, sf = 1.0;
+                        for (int b = 0; b < D; ++b) {
+                            V *= o.dl[b][cc[b]];
+                            if (b != a) sf *= o.dl[b][cc[b]];
+                        }
+                        long cidx = cell_int(&o, cc[0], cc[1], cc[2]);
+                        double sgn = side ? 1.0 : -1.0;
+                        for (int q = 0; q < Q; ++q) Fo_b[q] += sgn * dt / V * o.xi[q][a] * sf * lam[q * nc + cidx];
                     }
+                    const double* Fb = F5[a] + fi * Q;
+                    double rho, u[3], G[3];
                     accel_face(&o, cfg, Gext, a, c, gth, G);
-                    for (int b = 0; b < D; ++b) u[b] = (m[b] + rho0 * G[b] * h / 2.0) / rho0;
-                    /* step 7 reverse */
-                    double Fbb[MAXQ], rb = 0.0, ub[3] = {0, 0, 0}, Gbb[3] = {0, 0, 0};
+                    face_macro(&o, cfg, Fb, G, h, &rho, u);
+                    double rb = 0.0, ub[3] = {0, 0, 0}, Gbb[3] = {0, 0, 0};
                     for (int q = 0; q < Q; ++q) {
                         double dfr, dfu[3], dsr, dsu[3], dsg[3];
                         feq_partials(&o, cfg, q, rho, u, G, &dfr, dfu, &dsr, dsu, dsg);
-                        Fbb[q] = A7 * Fo_b[q];
+                        Fb5[a][fi * Q + q] = A7 * Fo_b[q];
                         rb += Fo_b[q] * (B7 * dfr + C7 * dsr);
                         for (int b = 0; b < D; ++b) {
                             ub[b] += Fo_b[q] * (B7 * dfu[b] + C7 * dsu[b]);
                             Gbb[b] += Fo_b[q] * C7 * dsg[b];
                         }
                     }
-                    /* step 6 reverse: u = (m + rho0 G h/2)/rho0 */
-                    double mb[3] = {0, 0, 0};
-                    for (int b = 0; b < D; ++b) { mb[b] = ub[b] / rho0; Gbb[b] += ub[b] * h / 2.0; }
+                    for (int b = 0; b < D; ++b) Gbb[b] += ub[b] * h / 2.0;
                     for (int q = 0; q < Q; ++q) {
-                        Fbb[q] += rb;
-                        for (int b = 0; b < D; ++b) Fbb[q] += o.xi[q][b] * mb[b];
+                        double v = rb;
+                        for (int b = 0; b < D; ++b) v += o.xi[q][b] * ub[b] / rho0;
+                        Fb5[a][fi * Q + q] += v;
                     }
-                    /* force at the face: G = gth (G0 + (1-w) G^_L + w G^_R) */
-                    {
-                        int cle[3] = {i, j, k};
-                        cle[a] = c[a] - 1;
-                        double w = o.w[a][c[a]];
-                        long Le = cell_ext(&o, cle[0], cle[1], cle[2]), Re = cell_ext(&o, c[0], c[1], c[2]);
-                        for (int b = 0; b < D; ++b) {
-                            Gb_sp[Le * 3 + b] += (1.0 - w) * gth * Gbb[b];
-                            Gb_sp[Re * 3 + b] += w * gth * Gbb[b];
-                        }
-                    }
-                    /* step 4 + 3 reverse: F = (1-w) fp_L + w fp_R - h sum_b xi_b sigma_b */
-                    int cle[3] = {i, j, k};
-                    cle[a] = c[a] - 1;
-                    long Le = cell_ext(&o, cle[0], cle[1], cle[2]), Re = cell_ext(&o, c[0], c[1], c[2]);
-                    double w = o.w[a][c[a]], gn = o.g[a][c[a]];
+                    for (int b = 0; b < D; ++b) Gbf[a][fi * 3 + b] += Gbb[b];
+                }
+    }
+
+    /* step 5 transposed: Fb5 of wall faces becomes the adjoint of F4; NEQ
+     * adds to the opposite interface of the wall cell */
+    for (int s = 0; s < 2 * D; ++s) {
+        int a = s / 2, hi = s % 2;
+        if (o.per[a]) continue;
+        int bc = cfg->bc[s], N = o.n[a];
+        int nsg = hi ? 1 : -1;
+        int lo[3] = {0, 0, 0}, up[3];
+        for (int b = 0; b < 3; ++b) up[b] = o.n[b] - 1;
+        lo[a] = up[a] = 0;
+        for (int k = lo[2]; k <= up[2]; ++k)
+            for (int j = lo[1]; j <= up[1]; ++j)
+                for (int i = lo[0]; i <= up[0]; ++i) {
+                    int cw[3] = {i, j, k}, co[3] = {i, j, k};
+                    cw[a] = hi ? N : 0;
+                    co[a] = hi ? N - 1 : 1;
+                    double* Bw = Fb5[a] + face_idx(&o, a, cw) * Q;
+                    double* Bo = Fb5[a] + face_idx(&o, a, co) * Q;
+                    double rep[MAXQ];
                     for (int q = 0; q < Q; ++q) {
-                        double Fq = Fbb[q];
-                        fpb[Le * Q + q] += (1.0 - w) * Fq;
-                        fpb[Re * Q + q] += w * Fq;
-                        double sa = -h * o.xi[q][a] * Fq;
-                        fpb[Re * Q + q] += gn * sa;
-                        fpb[Le * Q + q] -= gn * sa;
-                        for (int b = 0; b < D; ++b) {
-                            if (b == a) continue;
-                            double sb = -h * o.xi[q][b] * Fq / o.dl[b][c[b]];
-                            for (int up = 0; up < 2; ++up) {
-                                double sgn = up ? sb : -sb;
-                                int ce_[3] = {i, j, k};
-                                ce_[b] += up;
-                                double wa = o.w[a][ce_[a]], wb = o.w[b][ce_[b]];
-                                int c00[3] = {ce_[0], ce_[1], ce_[2]}, c10[3] = {ce_[0], ce_[1], ce_[2]};
-                                int c01[3] = {ce_[0], ce_[1], ce_[2]}, c11[3] = {ce_[0], ce_[1], ce_[2]};
-                                c00[a] -= 1; c00[b] -= 1; c10[b] -= 1; c01[a] -= 1;
-                                fpb[cell_ext(&o, c00[0], c00[1], c00[2]) * Q + q] += (1.0 - wb) * (1.0 - wa) * sgn;
-                                fpb[cell_ext(&o, c10[0], c10[1], c10[2]) * Q + q] += (1.0 - wb) * wa * sgn;
-                                fpb[cell_ext(&o, c01[0], c01[1], c01[2]) * Q + q] += wb * (1.0 - wa) * sgn;
-                                fpb[cell_ext(&o, c11[0], c11[1], c11[2]) * Q + q] += wb * wa * sgn;
-                            }
+                        rep[q] = (o.e[q][a] * nsg < 0) ? Bw[q] : 0.0;
+                        if (o.e[q][a] * nsg < 0) Bw[q] = 0.0;
+                    }
+                    if (bc == OR_BOUNCE_BACK) {
+                        for (int q = 0; q < Q; ++q)
+                            if (o.e[q][a] * nsg < 0) Bw[o.opp[q]] += rep[q];
+                    } else {
+                        const double* Fo = F4[a] + face_idx(&o, a, co) * Q;
+                        double rc, uc[3], Gb[3], ra, ua[3] = {0, 0, 0};
+                        accel_face(&o, cfg, Gext, a, co, gth, Gb);
+                        face_macro(&o, cfg, Fo, Gb, h, &rc, uc);
+                        const int vel = (bc == OR_NEQ_VELOCITY);
+                        if (vel) {
+                            ra = rc;
+                            for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
+                        } else {
+                            ra = rho0 + cfg->pw[s] / RT;
+                            for (int b = 0; b < D; ++b) ua[b] = uc[b];
                         }
+                        double rcb = 0.0, ucb[3] = {0, 0, 0};
+                        for (int q = 0; q < Q; ++q) {
+                            if (o.e[q][a] * nsg >= 0) continue;
+                            double dfr, dfu[3], dsr, dsu[3], dsg[3];
+                            /* + feq(ra, ua) */
+                            feq_partials(&o, cfg, q, ra, ua, Gb, &dfr, dfu, &dsr, dsu, dsg);
+                            if (vel) rcb += rep[q] * dfr;
+                            else
+                                for (int b = 0; b < D; ++b) ucb[b] += rep[q] * dfu[b];
+                            /* + Fo - feq(rc, uc) */
+                            Bo[q] += rep[q];
+                            feq_partials(&o, cfg, q, rc, uc, Gb, &dfr, dfu, &dsr, dsu, dsg);
+                            rcb -= rep[q] * dfr;
+                            for (int b = 0; b < D; ++b) ucb[b] -= rep[q] * dfu[b];
+                        }
+                        for (int q = 0; q < Q; ++q) {
+                            double v = rcb;
+                            for (int b = 0; b < D; ++b) v += o.xi[q][b] * ucb[b] / rho0;
+                            Bo[q] += v;
+                        }
+                        for (int b = 0; b < D; ++b) Gbf[a][face_idx(&o, a, co) * 3 + b] += ucb[b] * h / 2.0;
                     }
                 }
     }
 
-    /* step 2 reverse: ghosts are copies of wrapped cells; fold them back.
-     * Axes in reverse order of the forward fill. */
-    for (int a = D - 1; a >= 0; --a) {
-        int lo[3], hi[3];
-        for (int b = 0; b < 3; ++b) {
-            if (b >= D) { lo[b] = 0; hi[b] = 0; continue; }
-            if (b < a) { lo[b] = -1; hi[b] = o.n[b]; }
-            else { lo[b] = 0; hi[b] = o.n[b] - 1; }
-        }
-        int N = o.n[a];
-        for (int side = 0; side < 2; ++side) {
-            lo[a] = hi[a] = side ? N : -1;
-            for (int k = lo[2]; k <= hi[2]; ++k)
-                for (int j = lo[1]; j <= hi[1]; ++j)
-                    for (int i = lo[0]; i <= hi[0]; ++i) {
-                        int c0[3] = {i, j, k};
-                        c0[a] = side ? 0 : N - 1;
-                        long dst = cell_ext(&o, i, j, k), src = cell_ext(&o, c0[0], c0[1], c0[2]);
-                        for (int q = 0; q < Q; ++q) { fpb[src * Q + q] += fpb[dst * Q + q]; fpb[dst * Q + q] = 0; }
-                        for (int b = 0; b < 3; ++b) { Gb_sp[src * 3 + b] += Gb_sp[dst * 3 + b]; Gb_sp[dst * 3 + b] = 0; }
+    /* steps 3-4 transposed, and the face acceleration (interpolated like
+     * f-bar-plus along the normal, at t_n + h) */
+    for (int a = 0; a < D; ++a) {
+        int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
+        for (int k = 0; k < d2; ++k)
+            for (int j = 0; j < d1; ++j)
+                for (int i = 0; i < d0; ++i) {
+                    int c[3] = {i, j, k}, cl[3] = {i, j, k};
+                    cl[a] -= 1;
+                    long fi = face_idx(&o, a, c);
+                    for (int q = 0; q < Q; ++q) face_value_adj(&o, fpb, a, c, q, h, Fb5[a][fi * Q + q]);
+                    double w = o.w[a][c[a]];
+                    long Le = cell_ext(&o, cl[0], cl[1], cl[2]), Re = cell_ext(&o, c[0], c[1], c[2]);
+                    for (int b = 0; b < D; ++b) {
+                        Gb_sp[Le * 3 + b] += (1.0 - w) * gth * Gbf[a][fi * 3 + b];
+                        Gb_sp[Re * 3 + b] += w * gth * Gbf[a][fi * 3 + b];
                     }
-        }
+                }
     }
 
-    /* step 1 reverse */
+    /* step 2 transposed (f-bar-plus and the spatial force share the rule;
+     * the force adjoint is kept with 3 components per point) */
+    ghost_fold(&o, fpb, Q);
+    {
+        double* g = (double*)calloc((size_t)nce * D, sizeof(double));
+        for (long e = 0; e < nce; ++e)
+            for (int b = 0; b < D; ++b) g[e * D + b] = Gb_sp[e * 3 + b];
+        ghost_fold(&o, g, D);
+        for (long e = 0; e < nce; ++e)
+            for (int b = 0; b < 3; ++b) Gb_sp[e * 3 + b] = b < D ? g[e * D + b] : 0.0;
+        free(g);
+    }
+
+    /* step 1 transposed */
     for (int k = 0; k < o.n[2]; ++k)
         for (int j = 0; j < o.n[1]; ++j)
             for (int i = 0; i < o.n[0]; ++i) {
@@ -1016,7 +1194,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                         grad_force[b * nc + ci] += gt * Gcb[b] + Gb_sp[ce * 3 + b];
             }
 
-    for (int a = 0; a < 3; ++a) free(F[a]);
+    for (int a = 0; a < 3; ++a) { free(F4[a]); free(F5[a]); free(Fb5[a]); free(Gbf[a]); }
     free(fp); free(fpb); free(Gb_sp); free(rho_c); free(u_c); free(G_c); free(Gext);
     ctx_free(&o);
     return 0;

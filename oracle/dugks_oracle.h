@@ -70,7 +70,8 @@ int oracle_step(const oracle_cfg* cfg, const double* f_in, double* f_out,
 int oracle_moments(const oracle_cfg* cfg, const double* f, const double* force,
                    double t, double* rho, double* u, double* p, double* totals);
 
-/* reverse mode of one step on a fully periodic mesh:
+/* reverse mode of one step (incompressible model; any mesh and boundary
+ * set, walls included):
  *   lam_n      = (d f_{n+1} / d f_n)^T lam_np1
  *   grad_force += (d f_{n+1} / d force)^T lam_np1   (nullable) */
 int oracle_step_adjoint(const oracle_cfg* cfg, const double* f_n, const double* force,

@@ -40,9 +40,74 @@ def test_step_adjoint_dot_product(lat, stretch):
     assert rhs_g == pytest.approx(lhs_g, rel=1e-7)
 
 
-def test_step_adjoint_rejects_walls():
+LID = [[0, 0, 0], [0, 0, 0], [0, 0, 0], [0.05, 0, 0], [0, 0, 0], [0, 0, 0]]
+MOVING = [[0, 0.02, 0], [0, -0.01, 0], [0.03, 0, 0], [0.05, 0, 0], [0, 0, 0.01], [0.02, 0, 0]]
+
+
+def wall_setup(lat, bc, stretch=0, uw=LID, pw=(0,) * 6):
+    """small meshes with walls: every wall cell is next to a wall, a corner or
+    the opposite wall (n = 2 along some axes)"""
+    if lat == 9:
+        d = dict(lattice=9, n=(5, 4, 1), L=(5.0, 4.0, 1.0), mesh=(stretch, stretch, 0), k_stretch=1.5)
+    else:
+        d = dict(lattice=19, n=(3, 4, 2), L=(3.0, 4.0, 2.0), mesh=(stretch,) * 3, k_stretch=1.5)
+    d.update(rho0=1.0, RT=1 / 3, tau=0.45, dt=0.5, bc=bc, uw=uw, pw=list(pw), G=(1e-3, -5e-4, 2e-4),
+             omega=0.7, phase=0.3)
+    D, Q, shp = O.dims(d)
+    Gf = field(41, (D,) + shp, 2e-3)
+    f = perturb(42, O.init(d, rho=1 + field(43, shp, 0.02), u=field(44, (D,) + shp, 0.05), force=Gf), 1e-2)
+    return d, f, Gf
+
+
+WALL_CASES = [
+    (9, (1, 1, 1, 1, 0, 0), 0, LID, (0,) * 6),                       # NEQ velocity cavity
+    (9, (3, 3, 3, 3, 0, 0), 1, MOVING, (0,) * 6),                    # bounce-back, moving walls, tanh
+    (9, (2, 2, 3, 3, 0, 0), 0, LID, (3e-3, -2e-3, 0, 0, 0, 0)),      # NEQ pressure in x, BB in y
+    (9, (1, 3, 2, 1, 0, 0), 1, MOVING, (0, 0, 1e-3, 0, 0, 0)),       # every kind, tanh
+    (9, (0, 0, 1, 1, 0, 0), 1, LID, (0,) * 6),                       # periodic x, NEQ walls, tanh
+    (19, (1, 1, 1, 1, 1, 1), 0, LID, (0,) * 6),                      # NEQ cube
+    (19, (3, 2, 1, 3, 0, 0), 1, MOVING, (0, 2e-3, 0, 0, 0, 0)),      # mixed, periodic z, tanh
+]
+
+
+@pytest.mark.parametrize("lat,bc,stretch,uw,pw", WALL_CASES,
+                         ids=["q9-neq", "q9-bb-moving-tanh", "q9-neqp-bb", "q9-mixed-tanh", "q9-channel-tanh",
+                              "q19-neq", "q19-mixed-tanh"])
+def test_step_adjoint_dot_product_walls(lat, bc, stretch, uw, pw):
+    # reverse mode through the wall rules (Eqs. BB, NEQ), the ghost
+    # extrapolation and the stretched-mesh metrics, against central FD of
+    # the forward step (the step stays a polynomial in (f~, G^))
+    d, f, Gf = wall_setup(lat, bc, stretch, uw, pw)
+    t = 0.4
+    v = field(45, f.shape, 1.0)
+    w = field(46, f.shape, 1.0)
+    vg = field(47, Gf.shape, 1.0)
+    eps = 1e-5
+    jv = (O.step(d, f + eps * v, Gf, t) - O.step(d, f - eps * v, Gf, t)) / (2 * eps)
+    jg = (O.step(d, f, Gf + eps * 1e-2 * vg, t) - O.step(d, f, Gf - eps * 1e-2 * vg, t)) / (2 * eps * 1e-2)
+    gG = np.zeros_like(Gf)
+    jtw = O.step_adjoint(d, f, w, force=Gf, t=t, grad_force=gG)
+    assert np.vdot(v, jtw) == pytest.approx(np.vdot(jv, w), rel=5e-9)
+    assert np.vdot(vg, gG) == pytest.approx(np.vdot(jg, w), rel=1e-7)
+
+
+def test_step_adjoint_wall_columns_by_brute_force():
+    # full Jacobian columns of a tiny walled mesh: e_k^T J^T w for a few unit
+    # vectors e_k next to walls and corners, each against a central FD
+    d, f, Gf = wall_setup(9, (1, 3, 2, 1, 0, 0), 1, MOVING, (0, 0, 1e-3, 0, 0, 0))
+    w = field(48, f.shape, 1.0)
+    jtw = O.step_adjoint(d, f, w, force=Gf, t=0.4)
+    eps = 1e-5
+    for idx in [(1, 0, 0, 0), (5, 0, 3, 4), (8, 0, 0, 4), (2, 0, 3, 0), (0, 0, 1, 2)]:
+        e = np.zeros_like(f)
+        e[idx] = 1.0
+        col = (O.step(d, f + eps * e, Gf, 0.4) - O.step(d, f - eps * e, Gf, 0.4)) / (2 * eps)
+        assert jtw[idx] == pytest.approx(np.vdot(col, w), rel=1e-8, abs=1e-12)
+
+
+def test_step_adjoint_rejects_the_original_model():
     d, f, Gf = setup(9)
-    d["bc"] = (0, 0, 1, 1, 0, 0)
+    d["model"] = 1
     with pytest.raises(ValueError):
         O.step_adjoint(d, f, f)
 
