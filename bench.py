@@ -212,9 +212,10 @@ def bench_batched(dtype="f64", count=64, steps=100, warmup=5):
             "accuracy": "bitwise identical to the plain launches"}
 
 
-def bench_adjoint(n=256, steps=50, warmup=5):
-    """adjoint step vs forward step, D2Q9 n^2 periodic, FP64, tau = 1, with a
-    body-force field (the gradient workload)"""
+def bench_adjoint(n=256, steps=50, warmup=5, walls=False):
+    """adjoint step vs forward step, D2Q9 n^2, FP64, tau = 1, with a
+    body-force field (the gradient workload): periodic, or (walls) a
+    lid-driven cavity with NEQ walls on a tanh mesh (k = 1.5)"""
     import torch
 
     import paper_1411_6121_amd as M
@@ -222,6 +223,11 @@ def bench_adjoint(n=256, steps=50, warmup=5):
 
     cfg = dict(lattice=9, dtype="f64", n=(n, n, 1), L=(float(n), float(n), 1.0), rho0=1.0, RT=1 / 3, tau=1.0,
                dt=0.5, bc=(0,) * 6)
+    if walls:
+        uw = [[0.0] * 3 for _ in range(6)]
+        uw[3] = [0.05, 0.0, 0.0]
+        cfg.update(bc=(1, 1, 1, 1, 0, 0), uw=uw, mesh=(1, 1, 0), k_stretch=1.5)
+        cfg["dt"] = M.dugks_dt_from_cfl(cfg, 0.5)
     Q, D, shp = M.shape_of(cfg)
     Gf = torch.from_numpy(gaussian_bumps(7, n)).to("cuda")
     f = torch.empty((Q,) + shp, dtype=torch.float64, device="cuda")
@@ -245,7 +251,8 @@ def bench_adjoint(n=256, steps=50, warmup=5):
         ms_a = e0.elapsed_time(e1) / steps
     finally:
         M.dugks_destroy(ctx)
-    return {"workload": f"D2Q9 {n}^2 periodic, force field, f64", "ms_forward_step": round(ms_f, 4),
+    kind = "lid-driven cavity, NEQ walls, tanh mesh" if walls else "periodic"
+    return {"workload": f"D2Q9 {n}^2 {kind}, force field, f64", "ms_forward_step": round(ms_f, 4),
             "ms_adjoint_step": round(ms_a, 4), "ratio": round(ms_a / ms_f, 3)}
 
 
@@ -505,6 +512,7 @@ def main():
                          "hbm_frac": round(b27 / (ms27 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         also["batched"] = bench_batched()
         also["adjoint"] = bench_adjoint()
+        also["adjoint_walls"] = bench_adjoint(walls=True)
         res["also"] = also
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg)

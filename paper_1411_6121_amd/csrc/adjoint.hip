@@ -19,6 +19,8 @@
 //     the force-field gradient (cell term at t_n, face terms at t_n + h).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "ctx.hpp"
 #include "kernels_general.hpp"
 
@@ -361,6 +363,462 @@ __global__ __launch_bounds__(256) void k_phi_adj(const Inst<T>* __restrict__ Pp,
     phi_ext_body<LAT, T>(P, e, f, force, phi, gt);
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode on meshes with walls (and any mix of periodic and wall axes).
+// Every face of axis a, indices 0..n_a, is its own node (face n_a of a
+// periodic axis equals face 0 in the forward step and is transposed as a
+// face of its own), and the adjoint of f-bar-plus lives on the whole
+// ghost-extended grid; the ghost rule is transposed at the end.
+//   face pass   (per face): recompute F (steps 3-4) and the wall rule
+//                (step 5) at wall faces; reverse of the flux (adjacent
+//                interior cells only), of step 7 and of the face moments ->
+//                adjoint of F after step 5, and of the face acceleration;
+//   wall pass   (per wall line, both sides): transpose step 5 (bounce-back:
+//                permutation; NEQ: the replaced values depend on the values
+//                and moments of the opposite interface x_c of the wall cell);
+//   psi pass    (per extended point): psi_hat_a from the two faces of each
+//                axis, normal terms, 4/3 lam, d_hat_t, face-force adjoint;
+//   phi pass    (per extended point): phi_hat += cp d_hat(-t) + c0 d_hat +
+//                cm d_hat(+t);
+//   fold passes (axes in reverse order): transpose of the ghost rule;
+//   cell pass   (per cell): reverse of Eq. (f_bar_+) and of the macroscopic
+//                recovery -> lam_n and the force-field gradient.
+// ---------------------------------------------------------------------------
+
+// faces of axis A: n_A + 1 along A, n_b across
+template <typename T>
+__device__ __forceinline__ void face_dims(const Inst<T>& P, int A, int* F)
+{
+#pragma unroll
+    for (int b = 0; b < 3; ++b) F[b] = P.n[b] + (b == A ? 1 : 0);
+}
+template <typename T>
+__device__ __forceinline__ long long face_lin(const Inst<T>& P, int A, const int* c)
+{
+    int F[3];
+    face_dims(P, A, F);
+    return ((long long)c[2] * F[1] + c[1]) * F[0] + c[0];
+}
+template <typename T>
+__host__ __device__ inline long long face_total(const Inst<T>& P, int A)
+{
+    long long n = 1;
+    for (int b = 0; b < 3; ++b) n *= (long long)(P.n[b] + (b == A ? 1 : 0));
+    return n;
+}
+
+// F after steps 3-4 on face c (c[A] = face index) of axis A, all velocities
+template <class LAT, typename T, int A>
+__device__ __forceinline__ void face_recon_at(const Inst<T>& P, const T* __restrict__ phi, const int* c, T* out)
+{
+    GlobalPhi<LAT, T> ph{phi, P.ne, ext_idx<LAT, T>(P, c[0], c[1], c[2]), (long long)P.E[0],
+                         (long long)P.E[0] * P.E[1]};
+    CellMetric<T> ma{};
+    ma.wl = P.m[A].w[c[A]];
+    ma.gl = P.m[A].gn[c[A]];
+    const CellMetric<T> mx = A == 0 ? ma : load_metric(P, 0, c[0]);
+    const CellMetric<T> my = A == 1 ? ma : load_metric(P, 1, c[1]);
+    const CellMetric<T> mz = (A == 2 || LAT::D == 2) ? ma : load_metric(P, 2, c[2]);
+    recon_face_ct<LAT, T, GlobalPhi<LAT, T>, A>(P, ph, false, ma, mx, my, mz, out);
+}
+
+template <class LAT, typename T, int A>
+__global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ Pp, const T* __restrict__ phi,
+                                                   const T* __restrict__ force, const T* __restrict__ lam, T gth,
+                                                   T* __restrict__ fa, T* __restrict__ ga)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const long long nf = face_total(P, A);
+    const long long fi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (fi >= nf) return;
+    int F[3], c[3];
+    face_dims(P, A, F);
+    c[0] = (int)(fi % F[0]);
+    const long long r = fi / F[0];
+    c[1] = (int)(r % F[1]);
+    c[2] = (int)(r / F[1]);
+    const int n = P.n[A], f = c[A];
+    T fb[Q], G[3];
+    face_recon_at<LAT, T, A>(P, phi, c, fb);
+    const T w = P.m[A].w[f];
+    face_force<LAT, T>(P, force, A, f, w, c, gth, G);
+    const bool wlo = !P.per[A] && f == 0, whi = !P.per[A] && f == n;
+    if (wlo || whi) {
+        int co[3] = {c[0], c[1], c[2]};
+        co[A] = wlo ? 1 : n - 1;
+        T fo[Q], Go[3];
+        face_recon_at<LAT, T, A>(P, phi, co, fo);
+        face_force<LAT, T>(P, force, A, co[A], P.m[A].w[co[A]], co, gth, Go);
+        NeqInfo<LAT, T> info;
+        neq_capture<LAT, T>(P, A, fo, Go, info);
+        wall_rule<LAT, T>(P, wlo ? 2 * A : 2 * A + 1, fb, info);
+    }
+    T rho, u[3];
+    face_moments<LAT, T>(P, fb, G, rho, u);
+    // flux adjoint from the interior cells on either side
+    T fh[Q];
+    const T invRT = T(1) / P.RT;
+    int cl[3] = {c[0], c[1], c[2]};
+    cl[A] = f - 1;
+    const bool hasL = f >= 1, hasR = f <= n - 1;
+    const long long lidx = hasL ? int_idx(P, cl[0], cl[1], cl[2]) : 0;
+    const long long ridx = hasR ? int_idx(P, c[0], c[1], c[2]) : 0;
+    const T sL = hasL ? P.m[A].fdx[f - 1] : T(0);
+    const T sR = hasR ? P.m[A].fdx[f] : T(0);
+    T rb = T(0), ub[3] = {T(0), T(0), T(0)}, Gb[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        fh[q] = T(0);
+        if (LAT::e(q, A) == 0) continue;
+        const T lr = hasR ? sR * lam[(long long)q * P.nc + ridx] : T(0);
+        const T ll = hasL ? sL * lam[(long long)q * P.nc + lidx] : T(0);
+        fh[q] = T(LAT::e(q, A)) * P.c * (lr - ll);
+        const Partials<LAT, T> pd = partials<LAT, T>(q, rho, u, G, P.rho0, P.c, invRT);
+        rb += fh[q] * (P.B7 * pd.dfe_dr + P.C7 * pd.dS_dr);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ub[d] += fh[q] * (P.B7 * pd.dfe_du[d] + P.C7 * pd.dS_du[d]);
+            Gb[d] += fh[q] * P.C7 * pd.dS_dG[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) Gb[d] += T(0.5) * P.h * ub[d];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        T v = (T(1) - P.B7) * fh[q] + rb;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ub[d];
+            if (LAT::e(q, d) == -1) v -= P.c / P.rho0 * ub[d];
+        }
+        fa[(long long)q * nf + fi] = v;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) ga[(long long)d * nf + fi] = Gb[d];
+}
+
+// transpose of step 5 on both walls of the lines along A (one thread per
+// line, so that the two walls' contributions to the opposite interface of
+// a two-cell line are added by one thread)
+template <class LAT, typename T, int A>
+__global__ __launch_bounds__(256) void k_adjw_wall(const Inst<T>* __restrict__ Pp, const T* __restrict__ phi,
+                                                   const T* __restrict__ force, T gth, T* __restrict__ fa,
+                                                   T* __restrict__ ga)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const int n = P.n[A];
+    const long long nl = P.nc / n;
+    const long long li = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= nl) return;
+    int F[3];
+    face_dims(P, A, F);
+    // transverse coordinates of the line
+    int c[3] = {0, 0, 0};
+    {
+        long long r = li;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (b == A) continue;
+            c[b] = (int)(r % P.n[b]);
+            r /= P.n[b];
+        }
+    }
+    const long long nf = face_total(P, A);
+    const T invRT = T(1) / P.RT;
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+        const int s = 2 * A + side;
+        const int sg = side ? 1 : -1;  // outward normal sg e_A
+        int cw[3] = {c[0], c[1], c[2]}, co[3] = {c[0], c[1], c[2]};
+        cw[A] = side ? n : 0;
+        co[A] = side ? n - 1 : 1;
+        const long long fw = face_lin(P, A, cw), fo = face_lin(P, A, co);
+        T rep[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            rep[q] = T(0);
+            if (LAT::e(q, A) * sg < 0) {
+                rep[q] = fa[(long long)q * nf + fw];
+                fa[(long long)q * nf + fw] = T(0);
+            }
+        }
+        if (P.bc[s] == BC_BOUNCE_BACK) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (LAT::e(q, A) * sg < 0) fa[(long long)LAT::opp(q) * nf + fw] += rep[q];
+            continue;
+        }
+        T fo_v[Q], Go[3], rc, uc[3];
+        face_recon_at<LAT, T, A>(P, phi, co, fo_v);
+        face_force<LAT, T>(P, force, A, co[A], P.m[A].w[co[A]], co, gth, Go);
+        face_moments<LAT, T>(P, fo_v, Go, rc, uc);
+        const bool vel = P.bc[s] == BC_NEQ_VELOCITY;
+        T ra, ua[3] = {T(0), T(0), T(0)};
+        if (vel) {
+            ra = rc;
+#pragma unroll
+            for (int d = 0; d < D; ++d) ua[d] = P.uw[s][d];
+        } else {
+            ra = P.rhow[s];
+#pragma unroll
+            for (int d = 0; d < D; ++d) ua[d] = uc[d];
+        }
+        T rcb = T(0), ucb[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (LAT::e(q, A) * sg >= 0) continue;
+            const Partials<LAT, T> pa = partials<LAT, T>(q, ra, ua, Go, P.rho0, P.c, invRT);
+            if (vel) rcb += rep[q] * pa.dfe_dr;
+            else
+#pragma unroll
+                for (int d = 0; d < D; ++d) ucb[d] += rep[q] * pa.dfe_du[d];
+            const Partials<LAT, T> pc = partials<LAT, T>(q, rc, uc, Go, P.rho0, P.c, invRT);
+            rcb -= rep[q] * pc.dfe_dr;
+#pragma unroll
+            for (int d = 0; d < D; ++d) ucb[d] -= rep[q] * pc.dfe_du[d];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            T v = rep[q] + rcb;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ucb[d];
+                if (LAT::e(q, d) == -1) v -= P.c / P.rho0 * ucb[d];
+            }
+            fa[(long long)q * nf + fo] += v;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) ga[(long long)d * nf + fo] += T(0.5) * P.h * ucb[d];
+    }
+}
+
+// decode an extended-grid index into coordinates -1..n
+template <class LAT, typename T>
+__device__ __forceinline__ void ext_coords(const Inst<T>& P, long long e, int* x)
+{
+    x[0] = (int)(e % P.E[0]) - 1;
+    const long long r = e / P.E[0];
+    x[1] = (int)(r % P.E[1]) - 1;
+    x[2] = LAT::D == 3 ? (int)(r / P.E[1]) - 1 : 0;
+}
+
+struct AdjFaces {
+    const void* fa[3];
+    const void* ga[3];
+};
+
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp, AdjFaces AF,
+                                                  const T* __restrict__ lam, T gth, T* __restrict__ php,
+                                                  T* __restrict__ dhat, T* __restrict__ gext)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.ne) return;
+    int x[3];
+    ext_coords<LAT, T>(P, e, x);
+    bool in[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) in[b] = x[b] >= 0 && x[b] < P.n[b];
+    T psi[D][Q], ph[Q], gx[3] = {T(0), T(0), T(0)};
+    const bool interior = in[0] && in[1] && in[2];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) ph[q] = interior ? T(4.0 / 3.0) * lam[(long long)q * P.nc + int_idx(P, x[0], x[1], x[2])] : T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) psi[a][q] = T(0);
+        bool across = true;
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+            if (b != a && !in[b]) across = false;
+        if (!across) continue;
+        const T* fa = (const T*)AF.fa[a];
+        const T* ga = (const T*)AF.ga[a];
+        const long long nf = face_total(P, a);
+        // lower face (this point is its right cell) and upper face (left cell)
+        const int flo = x[a], fup = x[a] + 1;
+        const bool hlo = flo >= 0 && flo <= P.n[a], hup = fup >= 0 && fup <= P.n[a];
+        int cf[3] = {x[0], x[1], x[2]};
+        cf[a] = flo;
+        const long long ilo = hlo ? face_lin(P, a, cf) : 0;
+        cf[a] = fup;
+        const long long iup = hup ? face_lin(P, a, cf) : 0;
+        const T wlo = hlo ? P.m[a].w[flo] : T(0), wup = hup ? P.m[a].w[fup] : T(0);
+        const T glo = hlo ? P.m[a].gn[flo] : T(0), gup = hup ? P.m[a].gn[fup] : T(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const T blo = hlo ? fa[(long long)q * nf + ilo] : T(0);
+            const T bup = hup ? fa[(long long)q * nf + iup] : T(0);
+            psi[a][q] = wlo * blo + (T(1) - wup) * bup;
+            ph[q] += psi[a][q] + T(LAT::e(q, a)) * P.h * P.c * (gup * bup - glo * blo);
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const T blo = hlo ? ga[(long long)d * nf + ilo] : T(0);
+            const T bup = hup ? ga[(long long)d * nf + iup] : T(0);
+            gx[d] += gth * (wlo * blo + (T(1) - wup) * bup);
+        }
+    }
+    const long long stride = (long long)Q * P.ne;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            T dh = T(0);
+            if (LAT::e(q, t) != 0) {
+                T s = T(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    if (a != t) s += psi[a][q];
+                dh = -P.h * P.c * T(LAT::e(q, t)) * s;
+            }
+            dhat[t * stride + (long long)q * P.ne + e] = dh;
+        }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) php[(long long)q * P.ne + e] = ph[q];
+#pragma unroll
+    for (int d = 0; d < D; ++d) gext[(long long)d * P.ne + e] = gx[d];
+}
+
+// phi_hat(Y) += sum_t cp(Y-t) d_hat_t(Y-t) + c0(Y) d_hat_t(Y) + cm(Y+t) d_hat_t(Y+t),
+// each term where the derivative is taken (an interior coordinate along t)
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_phi(const Inst<T>* __restrict__ Pp, const T* __restrict__ dhat,
+                                                  T* __restrict__ php)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.ne) return;
+    int x[3];
+    ext_coords<LAT, T>(P, e, x);
+    const long long stride = (long long)Q * P.ne;
+    const long long st[3] = {1, (long long)P.E[0], (long long)P.E[0] * P.E[1]};
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const int n = P.n[t], xt = x[t];
+        const bool dm = xt - 1 >= 0 && xt - 1 < n;  // derivative taken at Y - t
+        const bool d0 = xt >= 0 && xt < n;
+        const bool dp = xt + 1 >= 0 && xt + 1 < n;
+        const T cpm = dm ? P.m[t].cp[xt - 1] : T(0);
+        const T c00 = d0 ? P.m[t].c0[xt] : T(0);
+        const T cmp = dp ? P.m[t].cm[xt + 1] : T(0);
+        const T* dt_ = dhat + t * stride;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (LAT::e(q, t) == 0) continue;
+            T v = T(0);
+            if (dm) v += cpm * dt_[(long long)q * P.ne + e - st[t]];
+            if (d0) v += c00 * dt_[(long long)q * P.ne + e];
+            if (dp) v += cmp * dt_[(long long)q * P.ne + e + st[t]];
+            php[(long long)q * P.ne + e] += v;
+        }
+    }
+}
+
+// transpose of the ghost rule along axis A for the NC components of v
+// (phi_hat: Q, face-force adjoint: D); points extended along the axes
+// before A, interior along A and the axes after it
+template <class LAT, typename T, int NC>
+__global__ __launch_bounds__(256) void k_adjw_fold(const Inst<T>* __restrict__ Pp, int A, T* __restrict__ v)
+{
+    const Inst<T>& P = *Pp;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.ne) return;
+    int x[3];
+    ext_coords<LAT, T>(P, e, x);
+    for (int b = A; b < LAT::D; ++b)
+        if (x[b] < 0 || x[b] >= P.n[b]) return;
+    const int n = P.n[A], xa = x[A];
+    const long long st = A == 0 ? 1LL : (A == 1 ? (long long)P.E[0] : (long long)P.E[0] * P.E[1]);
+    const long long glo = e - (long long)(xa + 1) * st;  // ghost -1 of this line
+    const long long ghi = e + (long long)(n - xa) * st;  // ghost n
+    T wl = T(0), wh = T(0);
+    if (P.per[A]) {
+        if (xa == n - 1) wl = T(1);
+        if (xa == 0) wh = T(1);
+    } else {
+        if (xa == 0) wl += T(1) - P.rlo[A];
+        if (xa == 1) wl += P.rlo[A];
+        if (xa == n - 1) wh += T(1) - P.rhi[A];
+        if (xa == n - 2) wh += P.rhi[A];
+    }
+    if (wl == T(0) && wh == T(0)) return;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        const long long o = (long long)m * P.ne;
+        v[o + e] += wl * v[o + glo] + wh * v[o + ghi];
+    }
+}
+
+// reverse of Eq. (f_bar_+) and the macroscopic recovery per cell
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ Pp, const T* __restrict__ f,
+                                                   const T* __restrict__ force, const T* __restrict__ lam,
+                                                   const T* __restrict__ php, const T* __restrict__ gext, T gt,
+                                                   T* __restrict__ lam_out, T* __restrict__ grad_force)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= P.nc) return;
+    int ci[3];
+    ci[0] = (int)(cidx % P.n[0]);
+    const long long r = cidx / P.n[0];
+    ci[1] = (int)(r % P.n[1]);
+    ci[2] = (int)(r / P.n[1]);
+    const long long e = ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]);
+    const T invRT = T(1) / P.RT;
+    T fv[Q], rho = T(0), j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        fv[q] = f[(long long)q * P.nc + cidx];
+        rho += fv[q];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (LAT::e(q, a) == 1) j[a] += fv[q];
+            if (LAT::e(q, a) == -1) j[a] -= fv[q];
+        }
+    }
+    T G[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        G[a] = gt * (P.G0[a] + (force ? force[(long long)a * P.nc + cidx] : T(0)));
+        u[a] = P.c * j[a] / P.rho0 + P.h * G[a];
+    }
+    T rb = T(0), ub[3] = {T(0), T(0), T(0)}, Gc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const T pb = php[(long long)q * P.ne + e];
+        const Partials<LAT, T> pd = partials<LAT, T>(q, rho, u, G, P.rho0, P.c, invRT);
+        rb += pb * (P.B1 * pd.dfe_dr + P.C1 * pd.dS_dr);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ub[d] += pb * (P.B1 * pd.dfe_du[d] + P.C1 * pd.dS_du[d]);
+            Gc[d] += pb * P.C1 * pd.dS_dG[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) Gc[d] += P.h * ub[d];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        T v = (T(1) - P.B1) * php[(long long)q * P.ne + e] + rb - T(1.0 / 3.0) * lam[(long long)q * P.nc + cidx];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ub[d];
+            if (LAT::e(q, d) == -1) v -= P.c / P.rho0 * ub[d];
+        }
+        lam_out[(long long)q * P.nc + cidx] = v;
+    }
+    if (grad_force)
+#pragma unroll
+        for (int d = 0; d < D; ++d) grad_force[(long long)d * P.nc + cidx] += gt * Gc[d] + gext[(long long)d * P.ne + e];
+}
+
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 
 template <class LAT, typename T>
@@ -401,6 +859,80 @@ static int adjoint_step(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const 
     return hip_check(ctx, hipGetLastError(), "adjoint launch");
 }
 
+template <class LAT, typename T, int A>
+static void launch_adjw_axis(const Inst<T>& P, const Inst<T>* Pd, const T* phi, const T* force, const T* lam,
+                             T gth, T* fa, T* ga, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_adjw_face<LAT, T, A>), dim3(nb256(face_total(P, A))), dim3(256), 0, st, Pd, phi, force,
+                       lam, gth, fa, ga);
+    if (!P.per[A])
+        hipLaunchKernelGGL((k_adjw_wall<LAT, T, A>), dim3(nb256(P.nc / P.n[A])), dim3(256), 0, st, Pd, phi, force,
+                           gth, fa, ga);
+}
+
+template <class LAT, typename T>
+static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const void* force, double t,
+                              const void* lam_np1, void* lam_n, void* grad_force, hipStream_t st)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const size_t es = sizeof(T);
+    size_t nfaces = 0;
+    for (int a = 0; a < D; ++a) nfaces += (size_t)face_total(P, a);
+    const size_t need = (size_t)P.ne * Q * es        // phi (extended)
+                        + nfaces * Q * es            // face adjoints
+                        + nfaces * D * es            // face-force adjoints
+                        + (size_t)P.ne * Q * es      // phi_hat (extended)
+                        + (size_t)D * P.ne * Q * es  // d_hat (extended)
+                        + (size_t)P.ne * D * es;     // force adjoint (extended)
+    if (ctx->adj_bytes < need) {
+        if (ctx->adj) (void)hipFree(ctx->adj);
+        ctx->adj = nullptr;
+        ctx->adj_bytes = 0;
+        if (hipMalloc(&ctx->adj, need) != hipSuccess) return fail(ctx, DUGKS_ENOMEM, "adjoint scratch allocation failed");
+        ctx->adj_bytes = need;
+    }
+    T* p = (T*)ctx->adj;
+    T* phi = p;
+    p += (size_t)P.ne * Q;
+    AdjFaces AF{};
+    T* fa[3] = {nullptr, nullptr, nullptr};
+    T* ga[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < D; ++a) {
+        fa[a] = p;
+        p += (size_t)face_total(P, a) * Q;
+    }
+    for (int a = 0; a < D; ++a) {
+        ga[a] = p;
+        p += (size_t)face_total(P, a) * D;
+    }
+    for (int a = 0; a < 3; ++a) {
+        AF.fa[a] = fa[a];
+        AF.ga[a] = ga[a];
+    }
+    T* php = p;
+    p += (size_t)P.ne * Q;
+    T* dhat = p;
+    p += (size_t)D * P.ne * Q;
+    T* gext = p;
+    const Inst<T>* Pd = (const Inst<T>*)ctx->inst_dev;
+    const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
+    const T* lam = (const T*)lam_np1;
+    hipLaunchKernelGGL((k_phi_adj<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, (const T*)fn, (const T*)force,
+                       phi, gt);
+    launch_adjw_axis<LAT, T, 0>(P, Pd, phi, (const T*)force, lam, gth, fa[0], ga[0], st);
+    launch_adjw_axis<LAT, T, 1>(P, Pd, phi, (const T*)force, lam, gth, fa[1], ga[1], st);
+    if constexpr (D == 3) launch_adjw_axis<LAT, T, 2>(P, Pd, phi, (const T*)force, lam, gth, fa[2], ga[2], st);
+    hipLaunchKernelGGL((k_adjw_psi<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, AF, lam, gth, php, dhat, gext);
+    hipLaunchKernelGGL((k_adjw_phi<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, (const T*)dhat, php);
+    for (int a = D - 1; a >= 0; --a) {
+        hipLaunchKernelGGL((k_adjw_fold<LAT, T, Q>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, a, php);
+        hipLaunchKernelGGL((k_adjw_fold<LAT, T, D>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, a, gext);
+    }
+    hipLaunchKernelGGL((k_adjw_cell<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)fn, (const T*)force,
+                       lam, (const T*)php, (const T*)gext, gt, (T*)lam_n, (T*)grad_force);
+    return hip_check(ctx, hipGetLastError(), "adjoint (walls) launch");
+}
+
 template <class LAT, typename T>
 static int init_vjp(dugks_ctx* ctx, const Inst<T>& P, const void* u, const void* force, double t0, const void* lam0,
                     void* grad_u, void* grad_force, hipStream_t st)
@@ -439,10 +971,23 @@ extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* f
         return fail(ctx, DUGKS_EUNSUPPORTED, "the adjoint is derived for the incompressible model");
     if (ctx->cfg.lattice == DUGKS_D3Q27) return fail(ctx, DUGKS_EUNSUPPORTED, "no D3Q27 adjoint");
     if (lam_n == f_n || lam_n == lam_np1) return fail(ctx, DUGKS_EINVAL, "lam_n must not alias f_n or lam_np1");
+    bool periodic = true;
     for (int s = 0; s < 2 * ctx->D; ++s)
-        if (ctx->cfg.bc[s] != DUGKS_PERIODIC)
-            return fail(ctx, DUGKS_EUNSUPPORTED, "the adjoint step supports fully periodic meshes only");
+        if (ctx->cfg.bc[s] != DUGKS_PERIODIC) periodic = false;
     const hipStream_t st = (hipStream_t)stream;
+    // meshes with walls: the general reverse pass (also taken on periodic
+    // meshes when DUGKS_ADJOINT_GENERAL=1, to cross-check it)
+    const char* gen = getenv("DUGKS_ADJOINT_GENERAL");
+    if (!periodic || (gen && gen[0] == '1')) {
+        if (ctx->cfg.lattice == DUGKS_D2Q9) {
+            if (ctx->cfg.dtype == DUGKS_F64)
+                return adjoint_step_walls<D2Q9, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+            return adjoint_step_walls<D2Q9, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+        }
+        if (ctx->cfg.dtype == DUGKS_F64)
+            return adjoint_step_walls<D3Q19, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+        return adjoint_step_walls<D3Q19, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+    }
     if (ctx->cfg.lattice == DUGKS_D2Q9) {
         if (ctx->cfg.dtype == DUGKS_F64) return adjoint_step<D2Q9, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
         return adjoint_step<D2Q9, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
