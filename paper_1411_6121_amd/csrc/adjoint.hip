@@ -19,6 +19,7 @@
 //     the force-field gradient (cell term at t_n, face terms at t_n + h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 
 #include "ctx.hpp"
@@ -373,16 +374,19 @@ __global__ __launch_bounds__(256) void k_phi_adj(const Inst<T>* __restrict__ Pp,
 //                (step 5) at wall faces; reverse of the flux (adjacent
 //                interior cells only), of step 7 and of the face moments ->
 //                adjoint of F after step 5, and of the face acceleration;
-//   wall pass   (per wall line, both sides): transpose step 5 (bounce-back:
-//                permutation; NEQ: the replaced values depend on the values
-//                and moments of the opposite interface x_c of the wall cell);
+//                At wall faces the same thread transposes step 5 (bounce-back:
+//                a permutation; NEQ: the replaced values depend on the values
+//                and moments of the opposite interface x_c of the wall cell,
+//                whose share is kept per line and side and added to x_c by
+//                the psi pass);
 //   psi pass    (per extended point): psi_hat_a from the two faces of each
 //                axis, normal terms, 4/3 lam, d_hat_t, face-force adjoint;
-//   phi pass    (per extended point): phi_hat += cp d_hat(-t) + c0 d_hat +
-//                cm d_hat(+t);
-//   fold passes (axes in reverse order): transpose of the ghost rule;
-//   cell pass   (per cell): reverse of Eq. (f_bar_+) and of the macroscopic
-//                recovery -> lam_n and the force-field gradient.
+//   cell pass   (per cell): phi_hat = psi-pass part + cp d_hat(-t) + c0 d_hat
+//                + cm d_hat(+t), gathered from the cell and from every ghost
+//                the ghost rule builds from it (its transpose, with the
+//                tensor-product weights of edges and corners); then the
+//                reverse of Eq. (f_bar_+) and of the macroscopic recovery ->
+//                lam_n and the force-field gradient.
 // ---------------------------------------------------------------------------
 
 // faces of axis A: n_A + 1 along A, n_b across
@@ -407,6 +411,21 @@ __host__ __device__ inline long long face_total(const Inst<T>& P, int A)
     return n;
 }
 
+// index of the line along axis A through the point c (its coordinates
+// across A, lowest axis fastest)
+template <typename T>
+__device__ __forceinline__ long long line_of(const Inst<T>& P, int A, const int* c)
+{
+    long long li = 0, m = 1;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (b == A) continue;
+        li += m * c[b];
+        m *= P.n[b];
+    }
+    return li;
+}
+
 // F after steps 3-4 on face c (c[A] = face index) of axis A, all velocities
 template <class LAT, typename T, int A>
 __device__ __forceinline__ void face_recon_at(const Inst<T>& P, const T* __restrict__ phi, const int* c, T* out)
@@ -423,14 +442,13 @@ __device__ __forceinline__ void face_recon_at(const Inst<T>& P, const T* __restr
 }
 
 template <class LAT, typename T, int A>
-__global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ Pp, const T* __restrict__ phi,
-                                                   const T* __restrict__ force, const T* __restrict__ lam, T gth,
-                                                   T* __restrict__ fa, T* __restrict__ ga)
+__device__ __forceinline__ void adjw_face_body(const Inst<T>& P, long long fi, const T* __restrict__ phi,
+                                               const T* __restrict__ force, const T* __restrict__ lam, T gth,
+                                               T* __restrict__ fa, T* __restrict__ ga, T* __restrict__ ex,
+                                               T* __restrict__ gx)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    const Inst<T>& P = *Pp;
     const long long nf = face_total(P, A);
-    const long long fi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (fi >= nf) return;
     int F[3], c[3];
     face_dims(P, A, F);
@@ -444,13 +462,14 @@ __global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ P
     const T w = P.m[A].w[f];
     face_force<LAT, T>(P, force, A, f, w, c, gth, G);
     const bool wlo = !P.per[A] && f == 0, whi = !P.per[A] && f == n;
+    NeqInfo<LAT, T> info;
+    T Go[3] = {T(0), T(0), T(0)};
     if (wlo || whi) {
         int co[3] = {c[0], c[1], c[2]};
         co[A] = wlo ? 1 : n - 1;
-        T fo[Q], Go[3];
+        T fo[Q];
         face_recon_at<LAT, T, A>(P, phi, co, fo);
         face_force<LAT, T>(P, force, A, co[A], P.m[A].w[co[A]], co, gth, Go);
-        NeqInfo<LAT, T> info;
         neq_capture<LAT, T>(P, A, fo, Go, info);
         wall_rule<LAT, T>(P, wlo ? 2 * A : 2 * A + 1, fb, info);
     }
@@ -464,15 +483,15 @@ __global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ P
     const bool hasL = f >= 1, hasR = f <= n - 1;
     const long long lidx = hasL ? int_idx(P, cl[0], cl[1], cl[2]) : 0;
     const long long ridx = hasR ? int_idx(P, c[0], c[1], c[2]) : 0;
-    const T sL = hasL ? P.m[A].fdx[f - 1] : T(0);
-    const T sR = hasR ? P.m[A].fdx[f] : T(0);
+    const T sL_ = P.m[A].fdx[hasL ? f - 1 : 0], sR_ = P.m[A].fdx[hasR ? f : 0];
+    const T sL = hasL ? sL_ : T(0), sR = hasR ? sR_ : T(0);
     T rb = T(0), ub[3] = {T(0), T(0), T(0)}, Gb[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         fh[q] = T(0);
         if (LAT::e(q, A) == 0) continue;
-        const T lr = hasR ? sR * lam[(long long)q * P.nc + ridx] : T(0);
-        const T ll = hasL ? sL * lam[(long long)q * P.nc + lidx] : T(0);
+        const T lr = sR * lam[(long long)q * P.nc + ridx];
+        const T ll = sL * lam[(long long)q * P.nc + lidx];
         fh[q] = T(LAT::e(q, A)) * P.c * (lr - ll);
         const Partials<LAT, T> pd = partials<LAT, T>(q, rho, u, G, P.rho0, P.c, invRT);
         rb += fh[q] * (P.B7 * pd.dfe_dr + P.C7 * pd.dS_dr);
@@ -484,6 +503,7 @@ __global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ P
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) Gb[d] += T(0.5) * P.h * ub[d];
+    T vb[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         T v = (T(1) - P.B7) * fh[q] + rb;
@@ -492,106 +512,108 @@ __global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ P
             if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ub[d];
             if (LAT::e(q, d) == -1) v -= P.c / P.rho0 * ub[d];
         }
-        fa[(long long)q * nf + fi] = v;
+        vb[q] = v;
     }
-#pragma unroll
-    for (int d = 0; d < D; ++d) ga[(long long)d * nf + fi] = Gb[d];
-}
-
-// transpose of step 5 on both walls of the lines along A (one thread per
-// line, so that the two walls' contributions to the opposite interface of
-// a two-cell line are added by one thread)
-template <class LAT, typename T, int A>
-__global__ __launch_bounds__(256) void k_adjw_wall(const Inst<T>* __restrict__ Pp, const T* __restrict__ phi,
-                                                   const T* __restrict__ force, T gth, T* __restrict__ fa,
-                                                   T* __restrict__ ga)
-{
-    constexpr int Q = LAT::Q, D = LAT::D;
-    const Inst<T>& P = *Pp;
-    const int n = P.n[A];
-    const long long nl = P.nc / n;
-    const long long li = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (li >= nl) return;
-    int F[3];
-    face_dims(P, A, F);
-    // transverse coordinates of the line
-    int c[3] = {0, 0, 0};
-    {
-        long long r = li;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            if (b == A) continue;
-            c[b] = (int)(r % P.n[b]);
-            r /= P.n[b];
-        }
-    }
-    const long long nf = face_total(P, A);
-    const T invRT = T(1) / P.RT;
-#pragma unroll 1
-    for (int side = 0; side < 2; ++side) {
-        const int s = 2 * A + side;
-        const int sg = side ? 1 : -1;  // outward normal sg e_A
-        int cw[3] = {c[0], c[1], c[2]}, co[3] = {c[0], c[1], c[2]};
-        cw[A] = side ? n : 0;
-        co[A] = side ? n - 1 : 1;
-        const long long fw = face_lin(P, A, cw), fo = face_lin(P, A, co);
+    if (wlo || whi) {
+        // transpose of step 5: vb becomes the adjoint of the values before the
+        // rule; NEQ contributions to the opposite interface x_c go to the
+        // line's slot of `ex`/`gx`, added to that face by the psi pass
+        const int s = wlo ? 2 * A : 2 * A + 1;
+        const int sg = wlo ? -1 : 1;  // outward normal sg e_A
         T rep[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             rep[q] = T(0);
             if (LAT::e(q, A) * sg < 0) {
-                rep[q] = fa[(long long)q * nf + fw];
-                fa[(long long)q * nf + fw] = T(0);
+                rep[q] = vb[q];
+                vb[q] = T(0);
             }
         }
+        T xo[Q], go[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < Q; ++q) xo[q] = T(0);
         if (P.bc[s] == BC_BOUNCE_BACK) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                if (LAT::e(q, A) * sg < 0) fa[(long long)LAT::opp(q) * nf + fw] += rep[q];
-            continue;
-        }
-        T fo_v[Q], Go[3], rc, uc[3];
-        face_recon_at<LAT, T, A>(P, phi, co, fo_v);
-        face_force<LAT, T>(P, force, A, co[A], P.m[A].w[co[A]], co, gth, Go);
-        face_moments<LAT, T>(P, fo_v, Go, rc, uc);
-        const bool vel = P.bc[s] == BC_NEQ_VELOCITY;
-        T ra, ua[3] = {T(0), T(0), T(0)};
-        if (vel) {
-            ra = rc;
-#pragma unroll
-            for (int d = 0; d < D; ++d) ua[d] = P.uw[s][d];
+                if (LAT::e(q, A) * sg < 0) vb[LAT::opp(q)] += rep[q];
         } else {
-            ra = P.rhow[s];
+            const bool vel = P.bc[s] == BC_NEQ_VELOCITY;
+            T ra, ua[3] = {T(0), T(0), T(0)};
+            if (vel) {
+                ra = info.rc;
 #pragma unroll
-            for (int d = 0; d < D; ++d) ua[d] = uc[d];
-        }
-        T rcb = T(0), ucb[3] = {T(0), T(0), T(0)};
+                for (int d = 0; d < D; ++d) ua[d] = P.uw[s][d];
+            } else {
+                ra = P.rhow[s];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (LAT::e(q, A) * sg >= 0) continue;
-            const Partials<LAT, T> pa = partials<LAT, T>(q, ra, ua, Go, P.rho0, P.c, invRT);
-            if (vel) rcb += rep[q] * pa.dfe_dr;
-            else
-#pragma unroll
-                for (int d = 0; d < D; ++d) ucb[d] += rep[q] * pa.dfe_du[d];
-            const Partials<LAT, T> pc = partials<LAT, T>(q, rc, uc, Go, P.rho0, P.c, invRT);
-            rcb -= rep[q] * pc.dfe_dr;
-#pragma unroll
-            for (int d = 0; d < D; ++d) ucb[d] -= rep[q] * pc.dfe_du[d];
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            T v = rep[q] + rcb;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ucb[d];
-                if (LAT::e(q, d) == -1) v -= P.c / P.rho0 * ucb[d];
+                for (int d = 0; d < D; ++d) ua[d] = info.uc[d];
             }
-            fa[(long long)q * nf + fo] += v;
-        }
+            T rcb = T(0), ucb[3] = {T(0), T(0), T(0)};
 #pragma unroll
-        for (int d = 0; d < D; ++d) ga[(long long)d * nf + fo] += T(0.5) * P.h * ucb[d];
+            for (int q = 0; q < Q; ++q) {
+                if (LAT::e(q, A) * sg >= 0) continue;
+                const Partials<LAT, T> pa = partials<LAT, T>(q, ra, ua, Go, P.rho0, P.c, invRT);
+                if (vel) rcb += rep[q] * pa.dfe_dr;
+                else
+#pragma unroll
+                    for (int d = 0; d < D; ++d) ucb[d] += rep[q] * pa.dfe_du[d];
+                const Partials<LAT, T> pc = partials<LAT, T>(q, info.rc, info.uc, Go, P.rho0, P.c, invRT);
+                rcb -= rep[q] * pc.dfe_dr;
+#pragma unroll
+                for (int d = 0; d < D; ++d) ucb[d] -= rep[q] * pc.dfe_du[d];
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                T v = rep[q] + rcb;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ucb[d];
+                    if (LAT::e(q, d) == -1) v -= P.c / P.rho0 * ucb[d];
+                }
+                xo[q] = v;
+            }
+#pragma unroll
+            for (int d = 0; d < D; ++d) go[d] = T(0.5) * P.h * ucb[d];
+        }
+        const long long nl = P.nc / n;
+        const long long li = line_of(P, A, c);
+        const long long slot = (wlo ? 0 : nl) + li;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) ex[(long long)q * 2 * nl + slot] = xo[q];
+#pragma unroll
+        for (int d = 0; d < D; ++d) gx[(long long)d * 2 * nl + slot] = go[d];
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fa[(long long)q * nf + fi] = vb[q];
+#pragma unroll
+    for (int d = 0; d < D; ++d) ga[(long long)d * nf + fi] = Gb[d];
+}
+
+// all axes in one launch: blockIdx.y = axis
+struct AdjFaces {
+    void* fa[3];
+    void* ga[3];
+    void* ex[3];  // per wall line and side: NEQ part of the adjoint of the opposite interface
+    void* gx[3];  // the same for its acceleration
+};
+
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_face(const Inst<T>* __restrict__ Pp, const T* __restrict__ phi,
+                                                   const T* __restrict__ force, const T* __restrict__ lam, T gth,
+                                                   AdjFaces AF)
+{
+    const Inst<T>& P = *Pp;
+    const long long fi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (a == 0)
+        adjw_face_body<LAT, T, 0>(P, fi, phi, force, lam, gth, (T*)AF.fa[0], (T*)AF.ga[0], (T*)AF.ex[0],
+                                  (T*)AF.gx[0]);
+    else if (a == 1)
+        adjw_face_body<LAT, T, 1>(P, fi, phi, force, lam, gth, (T*)AF.fa[1], (T*)AF.ga[1], (T*)AF.ex[1],
+                                  (T*)AF.gx[1]);
+    else if constexpr (LAT::D == 3)
+        adjw_face_body<LAT, T, 2>(P, fi, phi, force, lam, gth, (T*)AF.fa[2], (T*)AF.ga[2], (T*)AF.ex[2],
+                                  (T*)AF.gx[2]);
 }
 
 // decode an extended-grid index into coordinates -1..n
@@ -603,11 +625,6 @@ __device__ __forceinline__ void ext_coords(const Inst<T>& P, long long e, int* x
     x[1] = (int)(r % P.E[1]) - 1;
     x[2] = LAT::D == 3 ? (int)(r / P.E[1]) - 1 : 0;
 }
-
-struct AdjFaces {
-    const void* fa[3];
-    const void* ga[3];
-};
 
 template <class LAT, typename T>
 __global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp, AdjFaces AF,
@@ -625,8 +642,10 @@ __global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp
     for (int b = 0; b < 3; ++b) in[b] = x[b] >= 0 && x[b] < P.n[b];
     T psi[D][Q], ph[Q], gx[3] = {T(0), T(0), T(0)};
     const bool interior = in[0] && in[1] && in[2];
+    const long long ci = interior ? int_idx(P, x[0], x[1], x[2]) : 0;
+    const T l43 = interior ? T(4.0 / 3.0) : T(0);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) ph[q] = interior ? T(4.0 / 3.0) * lam[(long long)q * P.nc + int_idx(P, x[0], x[1], x[2])] : T(0);
+    for (int q = 0; q < Q; ++q) ph[q] = l43 * lam[(long long)q * P.nc + ci];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
 #pragma unroll
@@ -647,20 +666,54 @@ __global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp
         const long long ilo = hlo ? face_lin(P, a, cf) : 0;
         cf[a] = fup;
         const long long iup = hup ? face_lin(P, a, cf) : 0;
-        const T wlo = hlo ? P.m[a].w[flo] : T(0), wup = hup ? P.m[a].w[fup] : T(0);
-        const T glo = hlo ? P.m[a].gn[flo] : T(0), gup = hup ? P.m[a].gn[fup] : T(0);
+        // branch-free: clamped indices, zero weights where a face is absent
+        const T wlo_ = P.m[a].w[hlo ? flo : 0], wup_ = P.m[a].w[hup ? fup : 0];
+        const T glo_ = P.m[a].gn[hlo ? flo : 0], gup_ = P.m[a].gn[hup ? fup : 0];
+        const T klo = hlo ? T(1) : T(0), kup = hup ? T(1) : T(0);
+        const T wlo = klo * wlo_, cup = kup * (T(1) - wup_);
+        const T glo = klo * glo_, gup = kup * gup_;
+        // NEQ shares of the walls in faces 1 (low wall) and n-1 (high wall)
+        T xw[4] = {T(0), T(0), T(0), T(0)};  // lo face: low, high wall; up face: low, high wall
+        long long xs[4] = {0, 0, 0, 0};
+        const T* ex = (const T*)AF.ex[a];
+        const T* gxa = (const T*)AF.gx[a];
+        long long nl2 = 0;
+        const bool wall_axis = !P.per[a];
+        if (wall_axis) {
+            const long long nl = P.nc / P.n[a];
+            nl2 = 2 * nl;
+            const long long li = line_of(P, a, x);
+            xs[0] = li;
+            xs[1] = nl + li;
+            xs[2] = li;
+            xs[3] = nl + li;
+            xw[0] = (hlo && flo == 1) ? T(1) : T(0);
+            xw[1] = (hlo && flo == P.n[a] - 1) ? T(1) : T(0);
+            xw[2] = (hup && fup == 1) ? T(1) : T(0);
+            xw[3] = (hup && fup == P.n[a] - 1) ? T(1) : T(0);
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const T blo = hlo ? fa[(long long)q * nf + ilo] : T(0);
-            const T bup = hup ? fa[(long long)q * nf + iup] : T(0);
-            psi[a][q] = wlo * blo + (T(1) - wup) * bup;
+            T blo = fa[(long long)q * nf + ilo];
+            T bup = fa[(long long)q * nf + iup];
+            if (wall_axis) {
+                const T* eq = ex + (long long)q * nl2;
+                blo += xw[0] * eq[xs[0]] + xw[1] * eq[xs[1]];
+                bup += xw[2] * eq[xs[2]] + xw[3] * eq[xs[3]];
+            }
+            psi[a][q] = wlo * blo + cup * bup;
             ph[q] += psi[a][q] + T(LAT::e(q, a)) * P.h * P.c * (gup * bup - glo * blo);
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const T blo = hlo ? ga[(long long)d * nf + ilo] : T(0);
-            const T bup = hup ? ga[(long long)d * nf + iup] : T(0);
-            gx[d] += gth * (wlo * blo + (T(1) - wup) * bup);
+            T blo = ga[(long long)d * nf + ilo];
+            T bup = ga[(long long)d * nf + iup];
+            if (wall_axis) {
+                const T* gq = gxa + (long long)d * nl2;
+                blo += xw[0] * gq[xs[0]] + xw[1] * gq[xs[1]];
+                bup += xw[2] * gq[xs[2]] + xw[3] * gq[xs[3]];
+            }
+            gx[d] += gth * (wlo * blo + cup * bup);
         }
     }
     const long long stride = (long long)Q * P.ne;
@@ -684,83 +737,73 @@ __global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp
     for (int d = 0; d < D; ++d) gext[(long long)d * P.ne + e] = gx[d];
 }
 
-// phi_hat(Y) += sum_t cp(Y-t) d_hat_t(Y-t) + c0(Y) d_hat_t(Y) + cm(Y+t) d_hat_t(Y+t),
+// phi_hat at an extended point Y: the psi-pass part plus
+//   sum_t cp(Y-t) d_hat_t(Y-t) + c0(Y) d_hat_t(Y) + cm(Y+t) d_hat_t(Y+t),
 // each term where the derivative is taken (an interior coordinate along t)
 template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_adjw_phi(const Inst<T>* __restrict__ Pp, const T* __restrict__ dhat,
-                                                  T* __restrict__ php)
+__device__ __forceinline__ void phi_hat_at(const Inst<T>& P, const T* __restrict__ php, const T* __restrict__ dhat,
+                                           long long e, const int* x, T w, T* acc)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    const Inst<T>& P = *Pp;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= P.ne) return;
-    int x[3];
-    ext_coords<LAT, T>(P, e, x);
     const long long stride = (long long)Q * P.ne;
     const long long st[3] = {1, (long long)P.E[0], (long long)P.E[0] * P.E[1]};
 #pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] += w * php[(long long)q * P.ne + e];
+#pragma unroll
     for (int t = 0; t < D; ++t) {
         const int n = P.n[t], xt = x[t];
-        const bool dm = xt - 1 >= 0 && xt - 1 < n;  // derivative taken at Y - t
+        const bool dm = xt - 1 >= 0 && xt - 1 < n;
         const bool d0 = xt >= 0 && xt < n;
         const bool dp = xt + 1 >= 0 && xt + 1 < n;
-        const T cpm = dm ? P.m[t].cp[xt - 1] : T(0);
-        const T c00 = d0 ? P.m[t].c0[xt] : T(0);
-        const T cmp = dp ? P.m[t].cm[xt + 1] : T(0);
+        // branch-free: every load is of a valid element (indices clamped),
+        // terms that do not exist get weight 0, so all loads issue at once
+        const T cpm_ = P.m[t].cp[dm ? xt - 1 : 0], c00_ = P.m[t].c0[d0 ? xt : 0], cmp_ = P.m[t].cm[dp ? xt + 1 : 0];
+        const T cpm = dm ? cpm_ : T(0), c00 = d0 ? c00_ : T(0), cmp = dp ? cmp_ : T(0);
+        const long long em = dm ? e - st[t] : e, ep = dp ? e + st[t] : e;
         const T* dt_ = dhat + t * stride;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if (LAT::e(q, t) == 0) continue;
-            T v = T(0);
-            if (dm) v += cpm * dt_[(long long)q * P.ne + e - st[t]];
-            if (d0) v += c00 * dt_[(long long)q * P.ne + e];
-            if (dp) v += cmp * dt_[(long long)q * P.ne + e + st[t]];
-            php[(long long)q * P.ne + e] += v;
+            const T* dq = dt_ + (long long)q * P.ne;
+            acc[q] += w * (cpm * dq[em] + c00 * dq[e] + cmp * dq[ep]);
         }
     }
 }
 
-// transpose of the ghost rule along axis A for the NC components of v
-// (phi_hat: Q, face-force adjoint: D); points extended along the axes
-// before A, interior along A and the axes after it
-template <class LAT, typename T, int NC>
-__global__ __launch_bounds__(256) void k_adjw_fold(const Inst<T>* __restrict__ Pp, int A, T* __restrict__ v)
+// the points of axis a whose value the ghost rule (step 2) builds from the
+// cell with coordinate x along a, with their weights: the cell itself and
+// up to two ghosts (wall: linear extrapolation; periodic: copies)
+template <typename T>
+__device__ __forceinline__ int ghost_sources(const Inst<T>& P, int a, int x, int* y, T* k)
 {
-    const Inst<T>& P = *Pp;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= P.ne) return;
-    int x[3];
-    ext_coords<LAT, T>(P, e, x);
-    for (int b = A; b < LAT::D; ++b)
-        if (x[b] < 0 || x[b] >= P.n[b]) return;
-    const int n = P.n[A], xa = x[A];
-    const long long st = A == 0 ? 1LL : (A == 1 ? (long long)P.E[0] : (long long)P.E[0] * P.E[1]);
-    const long long glo = e - (long long)(xa + 1) * st;  // ghost -1 of this line
-    const long long ghi = e + (long long)(n - xa) * st;  // ghost n
-    T wl = T(0), wh = T(0);
-    if (P.per[A]) {
-        if (xa == n - 1) wl = T(1);
-        if (xa == 0) wh = T(1);
+    const int n = P.n[a];
+    int m = 0;
+    y[m] = x;
+    k[m++] = T(1);
+    if (P.per[a]) {
+        if (x == n - 1) { y[m] = -1; k[m++] = T(1); }
+        if (x == 0) { y[m] = n; k[m++] = T(1); }
     } else {
-        if (xa == 0) wl += T(1) - P.rlo[A];
-        if (xa == 1) wl += P.rlo[A];
-        if (xa == n - 1) wh += T(1) - P.rhi[A];
-        if (xa == n - 2) wh += P.rhi[A];
+        T kl = T(0), kh = T(0);
+        if (x == 0) kl += T(1) - P.rlo[a];
+        if (x == 1) kl += P.rlo[a];
+        if (x == n - 1) kh += T(1) - P.rhi[a];
+        if (x == n - 2) kh += P.rhi[a];
+        if (kl != T(0)) { y[m] = -1; k[m++] = kl; }
+        if (kh != T(0)) { y[m] = n; k[m++] = kh; }
     }
-    if (wl == T(0) && wh == T(0)) return;
-#pragma unroll
-    for (int m = 0; m < NC; ++m) {
-        const long long o = (long long)m * P.ne;
-        v[o + e] += wl * v[o + glo] + wh * v[o + ghi];
-    }
+    return m;
 }
 
-// reverse of Eq. (f_bar_+) and the macroscopic recovery per cell
+// per cell: phi_hat gathered from the cell and every ghost built from it
+// (transpose of step 2, tensor-product weights), then the reverse of Eq.
+// (f_bar_+) and of the macroscopic recovery -> lam_n and the force gradient
 template <class LAT, typename T>
 __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ Pp, const T* __restrict__ f,
                                                    const T* __restrict__ force, const T* __restrict__ lam,
-                                                   const T* __restrict__ php, const T* __restrict__ gext, T gt,
-                                                   T* __restrict__ lam_out, T* __restrict__ grad_force)
+                                                   const T* __restrict__ php, const T* __restrict__ dhat,
+                                                   const T* __restrict__ gext, T gt, T* __restrict__ lam_out,
+                                                   T* __restrict__ grad_force)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const Inst<T>& P = *Pp;
@@ -771,7 +814,34 @@ __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ P
     const long long r = cidx / P.n[0];
     ci[1] = (int)(r % P.n[1]);
     ci[2] = (int)(r / P.n[1]);
-    const long long e = ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]);
+    int ys[3][3], ms[3] = {1, 1, 1};
+    T ks[3][3];
+    ys[2][0] = 0;
+    ks[2][0] = T(1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) ms[a] = ghost_sources(P, a, ci[a], ys[a], ks[a]);
+    T pb[Q], gb[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) pb[q] = T(0);
+    if (ms[0] == 1 && ms[1] == 1 && ms[2] == 1) {  // no ghost is built from this cell
+        const long long e = ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]);
+        phi_hat_at<LAT, T>(P, php, dhat, e, ci, T(1), pb);
+#pragma unroll
+        for (int d = 0; d < D; ++d) gb[d] = gext[(long long)d * P.ne + e];
+    } else
+#pragma unroll 1
+    for (int i2 = 0; i2 < ms[2]; ++i2)
+#pragma unroll 1
+        for (int i1 = 0; i1 < ms[1]; ++i1)
+#pragma unroll 1
+            for (int i0 = 0; i0 < ms[0]; ++i0) {
+                const int y[3] = {ys[0][i0], ys[1][i1], ys[2][i2]};
+                const T w = ks[0][i0] * ks[1][i1] * ks[2][i2];
+                const long long e = ext_idx<LAT, T>(P, y[0], y[1], y[2]);
+                phi_hat_at<LAT, T>(P, php, dhat, e, y, w, pb);
+#pragma unroll
+                for (int d = 0; d < D; ++d) gb[d] += w * gext[(long long)d * P.ne + e];
+            }
     const T invRT = T(1) / P.RT;
     T fv[Q], rho = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -793,20 +863,19 @@ __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ P
     T rb = T(0), ub[3] = {T(0), T(0), T(0)}, Gc[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T pb = php[(long long)q * P.ne + e];
         const Partials<LAT, T> pd = partials<LAT, T>(q, rho, u, G, P.rho0, P.c, invRT);
-        rb += pb * (P.B1 * pd.dfe_dr + P.C1 * pd.dS_dr);
+        rb += pb[q] * (P.B1 * pd.dfe_dr + P.C1 * pd.dS_dr);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            ub[d] += pb * (P.B1 * pd.dfe_du[d] + P.C1 * pd.dS_du[d]);
-            Gc[d] += pb * P.C1 * pd.dS_dG[d];
+            ub[d] += pb[q] * (P.B1 * pd.dfe_du[d] + P.C1 * pd.dS_du[d]);
+            Gc[d] += pb[q] * P.C1 * pd.dS_dG[d];
         }
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) Gc[d] += P.h * ub[d];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        T v = (T(1) - P.B1) * php[(long long)q * P.ne + e] + rb - T(1.0 / 3.0) * lam[(long long)q * P.nc + cidx];
+        T v = (T(1) - P.B1) * pb[q] + rb - T(1.0 / 3.0) * lam[(long long)q * P.nc + cidx];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             if (LAT::e(q, d) == 1) v += P.c / P.rho0 * ub[d];
@@ -816,7 +885,7 @@ __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ P
     }
     if (grad_force)
 #pragma unroll
-        for (int d = 0; d < D; ++d) grad_force[(long long)d * P.nc + cidx] += gt * Gc[d] + gext[(long long)d * P.ne + e];
+        for (int d = 0; d < D; ++d) grad_force[(long long)d * P.nc + cidx] += gt * Gc[d] + gb[d];
 }
 
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
@@ -859,17 +928,6 @@ static int adjoint_step(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const 
     return hip_check(ctx, hipGetLastError(), "adjoint launch");
 }
 
-template <class LAT, typename T, int A>
-static void launch_adjw_axis(const Inst<T>& P, const Inst<T>* Pd, const T* phi, const T* force, const T* lam,
-                             T gth, T* fa, T* ga, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_adjw_face<LAT, T, A>), dim3(nb256(face_total(P, A))), dim3(256), 0, st, Pd, phi, force,
-                       lam, gth, fa, ga);
-    if (!P.per[A])
-        hipLaunchKernelGGL((k_adjw_wall<LAT, T, A>), dim3(nb256(P.nc / P.n[A])), dim3(256), 0, st, Pd, phi, force,
-                           gth, fa, ga);
-}
-
 template <class LAT, typename T>
 static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const void* force, double t,
                               const void* lam_np1, void* lam_n, void* grad_force, hipStream_t st)
@@ -878,9 +936,13 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
     const size_t es = sizeof(T);
     size_t nfaces = 0;
     for (int a = 0; a < D; ++a) nfaces += (size_t)face_total(P, a);
+    size_t nwall = 0;  // 2 sides x lines of each wall axis
+    for (int a = 0; a < D; ++a)
+        if (!P.per[a]) nwall += (size_t)(2 * (P.nc / P.n[a]));
     const size_t need = (size_t)P.ne * Q * es        // phi (extended)
                         + nfaces * Q * es            // face adjoints
                         + nfaces * D * es            // face-force adjoints
+                        + nwall * (Q + D) * es       // NEQ parts of the opposite interfaces
                         + (size_t)P.ne * Q * es      // phi_hat (extended)
                         + (size_t)D * P.ne * Q * es  // d_hat (extended)
                         + (size_t)P.ne * D * es;     // force adjoint (extended)
@@ -908,6 +970,16 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
     for (int a = 0; a < 3; ++a) {
         AF.fa[a] = fa[a];
         AF.ga[a] = ga[a];
+        AF.ex[a] = nullptr;
+        AF.gx[a] = nullptr;
+    }
+    for (int a = 0; a < D; ++a) {
+        if (P.per[a]) continue;
+        const size_t nw = (size_t)(2 * (P.nc / P.n[a]));
+        AF.ex[a] = p;
+        p += nw * Q;
+        AF.gx[a] = p;
+        p += nw * D;
     }
     T* php = p;
     p += (size_t)P.ne * Q;
@@ -917,19 +989,15 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
     const Inst<T>* Pd = (const Inst<T>*)ctx->inst_dev;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
     const T* lam = (const T*)lam_np1;
+    long long maxf = 0;
+    for (int a = 0; a < D; ++a) maxf = std::max(maxf, face_total(P, a));
     hipLaunchKernelGGL((k_phi_adj<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, (const T*)fn, (const T*)force,
                        phi, gt);
-    launch_adjw_axis<LAT, T, 0>(P, Pd, phi, (const T*)force, lam, gth, fa[0], ga[0], st);
-    launch_adjw_axis<LAT, T, 1>(P, Pd, phi, (const T*)force, lam, gth, fa[1], ga[1], st);
-    if constexpr (D == 3) launch_adjw_axis<LAT, T, 2>(P, Pd, phi, (const T*)force, lam, gth, fa[2], ga[2], st);
+    hipLaunchKernelGGL((k_adjw_face<LAT, T>), dim3(nb256(maxf), D), dim3(256), 0, st, Pd, (const T*)phi,
+                       (const T*)force, lam, gth, AF);
     hipLaunchKernelGGL((k_adjw_psi<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, AF, lam, gth, php, dhat, gext);
-    hipLaunchKernelGGL((k_adjw_phi<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, (const T*)dhat, php);
-    for (int a = D - 1; a >= 0; --a) {
-        hipLaunchKernelGGL((k_adjw_fold<LAT, T, Q>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, a, php);
-        hipLaunchKernelGGL((k_adjw_fold<LAT, T, D>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, a, gext);
-    }
     hipLaunchKernelGGL((k_adjw_cell<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)fn, (const T*)force,
-                       lam, (const T*)php, (const T*)gext, gt, (T*)lam_n, (T*)grad_force);
+                       lam, (const T*)php, (const T*)dhat, (const T*)gext, gt, (T*)lam_n, (T*)grad_force);
     return hip_check(ctx, hipGetLastError(), "adjoint (walls) launch");
 }
 
