@@ -3,7 +3,7 @@
  *
  * One time step of the incompressible discrete unified gas-kinetic scheme
  * with body force of Wu, Shi, Chai & Wang (arXiv:1411.6121), its adjoint,
- * and a batched form, for the D2Q9 and D3Q19 velocity sets on uniform and
+ * and a batched form, for the D2Q9, D3Q19 and D3Q27 velocity sets on uniform and
  * tanh-stretched Cartesian meshes.  Every stage runs in hand-written HIP
  * kernels; this header is the whole interface.
  *
@@ -213,12 +213,19 @@ int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, cons
                           double t_b, double* out_host, void* stream);
 
 /*
- * Reverse mode of one step on a fully periodic mesh (all sides
- * DUGKS_PERIODIC; other cases return DUGKS_EUNSUPPORTED):
+ * Reverse mode of one step (Appendix steps 1-9 transposed, incompressible
+ * model, D2Q9 and D3Q19) on any mesh and boundary set: periodic sides,
+ * bounce-back (Eq. BB) and NEQ velocity/pressure walls (Eq. NEQ), uniform
+ * or tanh-stretched axes:
  *   lam_n       = (d f_{n+1} / d f_n)^T lam_np1
  *   grad_force += (d f_{n+1} / d G^)^T lam_np1   (nullable, [D])
- * The forward intermediates are recomputed from f_n (no tape).  lam_n must
- * not alias f_n or lam_np1.  Asynchronous.
+ * The forward intermediates are recomputed from f_n (no tape).  Fully
+ * periodic meshes take a three-pass gather form; meshes with walls a
+ * gather form over every face and the ghost-extended grid (the ghost rule
+ * of step 2 is transposed).  The scratch (about (2 + D) Q values per
+ * extended cell plus (Q + D) per face and per cell) is allocated on first
+ * use and kept by the context.  lam_n must not alias f_n or lam_np1.  The original-model
+ * variant and D3Q27 return DUGKS_EUNSUPPORTED.  Asynchronous.
  */
 int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
                        const void* lam_np1, void* lam_n, void* grad_force, void* stream);

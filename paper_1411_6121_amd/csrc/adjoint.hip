@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <utility>
 
 #include "ctx.hpp"
 #include "kernels_general.hpp"
@@ -379,14 +380,16 @@ __global__ __launch_bounds__(256) void k_phi_adj(const Inst<T>* __restrict__ Pp,
 //                and moments of the opposite interface x_c of the wall cell,
 //                whose share is kept per line and side and added to x_c by
 //                the psi pass);
-//   psi pass    (per extended point): psi_hat_a from the two faces of each
-//                axis, normal terms, 4/3 lam, d_hat_t, face-force adjoint;
-//   cell pass   (per cell): phi_hat = psi-pass part + cp d_hat(-t) + c0 d_hat
-//                + cm d_hat(+t), gathered from the cell and from every ghost
-//                the ghost rule builds from it (its transpose, with the
-//                tensor-product weights of edges and corners); then the
-//                reverse of Eq. (f_bar_+) and of the macroscopic recovery ->
-//                lam_n and the force-field gradient.
+//   psi pass    (per extended point and velocity): psi_hat_a from the two
+//                faces of each axis, normal terms, 4/3 lam, d_hat_t; the
+//                face-force adjoint;
+//   gather pass (per cell and velocity): phi_hat = psi-pass part + cp
+//                d_hat(-t) + c0 d_hat + cm d_hat(+t), gathered from the cell
+//                and from every ghost the ghost rule builds from it (its
+//                transpose, with the tensor-product weights of edges and
+//                corners);
+//   cell pass   (per cell): reverse of Eq. (f_bar_+) and of the macroscopic
+//                recovery -> lam_n and the force-field gradient.
 // ---------------------------------------------------------------------------
 
 // faces of axis A: n_A + 1 along A, n_b across
@@ -626,37 +629,31 @@ __device__ __forceinline__ void ext_coords(const Inst<T>& P, long long e, int* x
     x[2] = LAT::D == 3 ? (int)(r / P.E[1]) - 1 : 0;
 }
 
-template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp, AdjFaces AF,
-                                                  const T* __restrict__ lam, T gth, T* __restrict__ php,
-                                                  T* __restrict__ dhat, T* __restrict__ gext)
+// psi pass for one velocity q (compile time) at extended point e; the
+// threads with q = 0 also gather the face-force adjoint
+template <class LAT, typename T, int q>
+__device__ __forceinline__ void adjw_psi_q(const Inst<T>& P, const AdjFaces& AF, const T* __restrict__ lam, T gth,
+                                           long long e, T* __restrict__ php, T* __restrict__ dhat,
+                                           T* __restrict__ gext)
 {
-    constexpr int Q = LAT::Q, D = LAT::D;
-    const Inst<T>& P = *Pp;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= P.ne) return;
+    constexpr int D = LAT::D;
     int x[3];
     ext_coords<LAT, T>(P, e, x);
     bool in[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) in[b] = x[b] >= 0 && x[b] < P.n[b];
-    T psi[D][Q], ph[Q], gx[3] = {T(0), T(0), T(0)};
     const bool interior = in[0] && in[1] && in[2];
     const long long ci = interior ? int_idx(P, x[0], x[1], x[2]) : 0;
-    const T l43 = interior ? T(4.0 / 3.0) : T(0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) ph[q] = l43 * lam[(long long)q * P.nc + ci];
+    T ph = (interior ? T(4.0 / 3.0) : T(0)) * lam[(long long)q * P.nc + ci];
+    T psi[3] = {T(0), T(0), T(0)}, gx[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) psi[a][q] = T(0);
         bool across = true;
 #pragma unroll
         for (int b = 0; b < D; ++b)
             if (b != a && !in[b]) across = false;
         if (!across) continue;
         const T* fa = (const T*)AF.fa[a];
-        const T* ga = (const T*)AF.ga[a];
         const long long nf = face_total(P, a);
         // lower face (this point is its right cell) and upper face (left cell)
         const int flo = x[a], fup = x[a] + 1;
@@ -673,11 +670,8 @@ __global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp
         const T wlo = klo * wlo_, cup = kup * (T(1) - wup_);
         const T glo = klo * glo_, gup = kup * gup_;
         // NEQ shares of the walls in faces 1 (low wall) and n-1 (high wall)
-        T xw[4] = {T(0), T(0), T(0), T(0)};  // lo face: low, high wall; up face: low, high wall
-        long long xs[4] = {0, 0, 0, 0};
-        const T* ex = (const T*)AF.ex[a];
-        const T* gxa = (const T*)AF.gx[a];
-        long long nl2 = 0;
+        T xw[4] = {T(0), T(0), T(0), T(0)};
+        long long xs[4] = {0, 0, 0, 0}, nl2 = 0;
         const bool wall_axis = !P.per[a];
         if (wall_axis) {
             const long long nl = P.nc / P.n[a];
@@ -692,82 +686,95 @@ __global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp
             xw[2] = (hup && fup == 1) ? T(1) : T(0);
             xw[3] = (hup && fup == P.n[a] - 1) ? T(1) : T(0);
         }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            T blo = fa[(long long)q * nf + ilo];
-            T bup = fa[(long long)q * nf + iup];
-            if (wall_axis) {
-                const T* eq = ex + (long long)q * nl2;
-                blo += xw[0] * eq[xs[0]] + xw[1] * eq[xs[1]];
-                bup += xw[2] * eq[xs[2]] + xw[3] * eq[xs[3]];
-            }
-            psi[a][q] = wlo * blo + cup * bup;
-            ph[q] += psi[a][q] + T(LAT::e(q, a)) * P.h * P.c * (gup * bup - glo * blo);
+        T blo = fa[(long long)q * nf + ilo];
+        T bup = fa[(long long)q * nf + iup];
+        if (wall_axis) {
+            const T* eq = (const T*)AF.ex[a] + (long long)q * nl2;
+            blo += xw[0] * eq[xs[0]] + xw[1] * eq[xs[1]];
+            bup += xw[2] * eq[xs[2]] + xw[3] * eq[xs[3]];
         }
+        psi[a] = wlo * blo + cup * bup;
+        ph += psi[a] + T(LAT::e(q, a)) * P.h * P.c * (gup * bup - glo * blo);
+        if constexpr (q == 0) {
+            const T* ga = (const T*)AF.ga[a];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            T blo = ga[(long long)d * nf + ilo];
-            T bup = ga[(long long)d * nf + iup];
-            if (wall_axis) {
-                const T* gq = gxa + (long long)d * nl2;
-                blo += xw[0] * gq[xs[0]] + xw[1] * gq[xs[1]];
-                bup += xw[2] * gq[xs[2]] + xw[3] * gq[xs[3]];
+            for (int d = 0; d < D; ++d) {
+                T glo_d = ga[(long long)d * nf + ilo];
+                T gup_d = ga[(long long)d * nf + iup];
+                if (wall_axis) {
+                    const T* gq = (const T*)AF.gx[a] + (long long)d * nl2;
+                    glo_d += xw[0] * gq[xs[0]] + xw[1] * gq[xs[1]];
+                    gup_d += xw[2] * gq[xs[2]] + xw[3] * gq[xs[3]];
+                }
+                gx[d] += gth * (wlo * glo_d + cup * gup_d);
             }
-            gx[d] += gth * (wlo * blo + cup * bup);
         }
     }
-    const long long stride = (long long)Q * P.ne;
-#pragma unroll
-    for (int t = 0; t < D; ++t)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            T dh = T(0);
-            if (LAT::e(q, t) != 0) {
-                T s = T(0);
-#pragma unroll
-                for (int a = 0; a < D; ++a)
-                    if (a != t) s += psi[a][q];
-                dh = -P.h * P.c * T(LAT::e(q, t)) * s;
-            }
-            dhat[t * stride + (long long)q * P.ne + e] = dh;
-        }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) php[(long long)q * P.ne + e] = ph[q];
-#pragma unroll
-    for (int d = 0; d < D; ++d) gext[(long long)d * P.ne + e] = gx[d];
-}
-
-// phi_hat at an extended point Y: the psi-pass part plus
-//   sum_t cp(Y-t) d_hat_t(Y-t) + c0(Y) d_hat_t(Y) + cm(Y+t) d_hat_t(Y+t),
-// each term where the derivative is taken (an interior coordinate along t)
-template <class LAT, typename T>
-__device__ __forceinline__ void phi_hat_at(const Inst<T>& P, const T* __restrict__ php, const T* __restrict__ dhat,
-                                           long long e, const int* x, T w, T* acc)
-{
-    constexpr int Q = LAT::Q, D = LAT::D;
-    const long long stride = (long long)Q * P.ne;
-    const long long st[3] = {1, (long long)P.E[0], (long long)P.E[0] * P.E[1]};
-#pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] += w * php[(long long)q * P.ne + e];
+    const long long stride = (long long)LAT::Q * P.ne;
 #pragma unroll
     for (int t = 0; t < D; ++t) {
+        T dh = T(0);
+        if (LAT::e(q, t) != 0) {
+            T sp = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                if (a != t) sp += psi[a];
+            dh = -P.h * P.c * T(LAT::e(q, t)) * sp;
+        }
+        dhat[t * stride + (long long)q * P.ne + e] = dh;
+    }
+    php[(long long)q * P.ne + e] = ph;
+    if constexpr (q == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) gext[(long long)d * P.ne + e] = gx[d];
+}
+
+template <class LAT, typename T, int... Is>
+__device__ __forceinline__ void adjw_psi_dispatch(int q, std::integer_sequence<int, Is...>, const Inst<T>& P,
+                                                  const AdjFaces& AF, const T* __restrict__ lam, T gth, long long e,
+                                                  T* php, T* dhat, T* gext)
+{
+    ((q == Is ? adjw_psi_q<LAT, T, Is>(P, AF, lam, gth, e, php, dhat, gext) : void()), ...);
+}
+
+// one thread per (extended point, velocity): blockIdx.y = velocity
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_psi(const Inst<T>* __restrict__ Pp, AdjFaces AF,
+                                                  const T* __restrict__ lam, T gth, T* __restrict__ php,
+                                                  T* __restrict__ dhat, T* __restrict__ gext)
+{
+    const Inst<T>& P = *Pp;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.ne) return;
+    adjw_psi_dispatch<LAT, T>((int)blockIdx.y, std::make_integer_sequence<int, LAT::Q>{}, P, AF, lam, gth, e, php,
+                              dhat, gext);
+}
+
+// phi_hat of one velocity at an extended point Y: the psi-pass part plus
+//   sum_t cp(Y-t) d_hat_t(Y-t) + c0(Y) d_hat_t(Y) + cm(Y+t) d_hat_t(Y+t)
+template <class LAT, typename T, int q>
+__device__ __forceinline__ T phi_hat_q(const Inst<T>& P, const T* __restrict__ php, const T* __restrict__ dhat,
+                                       long long e, const int* x)
+{
+    constexpr int D = LAT::D;
+    const long long stride = (long long)LAT::Q * P.ne;
+    const long long st[3] = {1, (long long)P.E[0], (long long)P.E[0] * P.E[1]};
+    T acc = php[(long long)q * P.ne + e];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        if (LAT::e(q, t) == 0) continue;
         const int n = P.n[t], xt = x[t];
         const bool dm = xt - 1 >= 0 && xt - 1 < n;
         const bool d0 = xt >= 0 && xt < n;
         const bool dp = xt + 1 >= 0 && xt + 1 < n;
-        // branch-free: every load is of a valid element (indices clamped),
-        // terms that do not exist get weight 0, so all loads issue at once
+        // branch-free: clamped indices, zero weights for absent terms
         const T cpm_ = P.m[t].cp[dm ? xt - 1 : 0], c00_ = P.m[t].c0[d0 ? xt : 0], cmp_ = P.m[t].cm[dp ? xt + 1 : 0];
         const T cpm = dm ? cpm_ : T(0), c00 = d0 ? c00_ : T(0), cmp = dp ? cmp_ : T(0);
         const long long em = dm ? e - st[t] : e, ep = dp ? e + st[t] : e;
-        const T* dt_ = dhat + t * stride;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (LAT::e(q, t) == 0) continue;
-            const T* dq = dt_ + (long long)q * P.ne;
-            acc[q] += w * (cpm * dq[em] + c00 * dq[e] + cmp * dq[ep]);
-        }
+        const T* dq = dhat + t * stride + (long long)q * P.ne;
+        acc += cpm * dq[em] + c00 * dq[e] + cmp * dq[ep];
     }
+    return acc;
 }
 
 // the points of axis a whose value the ghost rule (step 2) builds from the
@@ -795,20 +802,15 @@ __device__ __forceinline__ int ghost_sources(const Inst<T>& P, int a, int x, int
     return m;
 }
 
-// per cell: phi_hat gathered from the cell and every ghost built from it
-// (transpose of step 2, tensor-product weights), then the reverse of Eq.
-// (f_bar_+) and of the macroscopic recovery -> lam_n and the force gradient
-template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ Pp, const T* __restrict__ f,
-                                                   const T* __restrict__ force, const T* __restrict__ lam,
-                                                   const T* __restrict__ php, const T* __restrict__ dhat,
-                                                   const T* __restrict__ gext, T gt, T* __restrict__ lam_out,
-                                                   T* __restrict__ grad_force)
+// phi_hat of velocity q at an interior cell, gathered from the cell and every
+// ghost the ghost rule builds from it (transpose of step 2, tensor-product
+// weights); the q = 0 threads gather the force adjoint likewise
+template <class LAT, typename T, int q>
+__device__ __forceinline__ void adjw_gather_q(const Inst<T>& P, long long cidx, const T* __restrict__ php,
+                                              const T* __restrict__ dhat, const T* __restrict__ gext,
+                                              T* __restrict__ pin, T* __restrict__ gin)
 {
-    constexpr int Q = LAT::Q, D = LAT::D;
-    const Inst<T>& P = *Pp;
-    const long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cidx >= P.nc) return;
+    constexpr int D = LAT::D;
     int ci[3];
     ci[0] = (int)(cidx % P.n[0]);
     const long long r = cidx / P.n[0];
@@ -820,28 +822,72 @@ __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ P
     ks[2][0] = T(1);
 #pragma unroll
     for (int a = 0; a < D; ++a) ms[a] = ghost_sources(P, a, ci[a], ys[a], ks[a]);
-    T pb[Q], gb[3] = {T(0), T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < Q; ++q) pb[q] = T(0);
+    T pb, gb[3] = {T(0), T(0), T(0)};
     if (ms[0] == 1 && ms[1] == 1 && ms[2] == 1) {  // no ghost is built from this cell
         const long long e = ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]);
-        phi_hat_at<LAT, T>(P, php, dhat, e, ci, T(1), pb);
+        pb = phi_hat_q<LAT, T, q>(P, php, dhat, e, ci);
+        if constexpr (q == 0)
 #pragma unroll
-        for (int d = 0; d < D; ++d) gb[d] = gext[(long long)d * P.ne + e];
-    } else
+            for (int d = 0; d < D; ++d) gb[d] = gext[(long long)d * P.ne + e];
+    } else {
+        pb = T(0);
 #pragma unroll 1
-    for (int i2 = 0; i2 < ms[2]; ++i2)
+        for (int i2 = 0; i2 < ms[2]; ++i2)
 #pragma unroll 1
-        for (int i1 = 0; i1 < ms[1]; ++i1)
+            for (int i1 = 0; i1 < ms[1]; ++i1)
 #pragma unroll 1
-            for (int i0 = 0; i0 < ms[0]; ++i0) {
-                const int y[3] = {ys[0][i0], ys[1][i1], ys[2][i2]};
-                const T w = ks[0][i0] * ks[1][i1] * ks[2][i2];
-                const long long e = ext_idx<LAT, T>(P, y[0], y[1], y[2]);
-                phi_hat_at<LAT, T>(P, php, dhat, e, y, w, pb);
+                for (int i0 = 0; i0 < ms[0]; ++i0) {
+                    const int y[3] = {ys[0][i0], ys[1][i1], ys[2][i2]};
+                    const T w = ks[0][i0] * ks[1][i1] * ks[2][i2];
+                    const long long e = ext_idx<LAT, T>(P, y[0], y[1], y[2]);
+                    pb += w * phi_hat_q<LAT, T, q>(P, php, dhat, e, y);
+                    if constexpr (q == 0)
 #pragma unroll
-                for (int d = 0; d < D; ++d) gb[d] += w * gext[(long long)d * P.ne + e];
-            }
+                        for (int d = 0; d < D; ++d) gb[d] += w * gext[(long long)d * P.ne + e];
+                }
+    }
+    pin[(long long)q * P.nc + cidx] = pb;
+    if constexpr (q == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) gin[(long long)d * P.nc + cidx] = gb[d];
+}
+
+template <class LAT, typename T, int... Is>
+__device__ __forceinline__ void adjw_gather_dispatch(int q, std::integer_sequence<int, Is...>, const Inst<T>& P,
+                                                     long long cidx, const T* php, const T* dhat, const T* gext,
+                                                     T* pin, T* gin)
+{
+    ((q == Is ? adjw_gather_q<LAT, T, Is>(P, cidx, php, dhat, gext, pin, gin) : void()), ...);
+}
+
+// one thread per (cell, velocity): blockIdx.y = velocity
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_gather(const Inst<T>* __restrict__ Pp, const T* __restrict__ php,
+                                                     const T* __restrict__ dhat, const T* __restrict__ gext,
+                                                     T* __restrict__ pin, T* __restrict__ gin)
+{
+    const Inst<T>& P = *Pp;
+    const long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= P.nc) return;
+    adjw_gather_dispatch<LAT, T>((int)blockIdx.y, std::make_integer_sequence<int, LAT::Q>{}, P, cidx, php, dhat,
+                                 gext, pin, gin);
+}
+
+// per cell: reverse of Eq. (f_bar_+) and of the macroscopic recovery ->
+// lam_n and the force-field gradient
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ Pp, const T* __restrict__ f,
+                                                   const T* __restrict__ force, const T* __restrict__ lam,
+                                                   const T* __restrict__ pin, const T* __restrict__ gin, T gt,
+                                                   T* __restrict__ lam_out, T* __restrict__ grad_force)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= P.nc) return;
+    T pb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) pb[q] = pin[(long long)q * P.nc + cidx];
     const T invRT = T(1) / P.RT;
     T fv[Q], rho = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -885,7 +931,7 @@ __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ P
     }
     if (grad_force)
 #pragma unroll
-        for (int d = 0; d < D; ++d) grad_force[(long long)d * P.nc + cidx] += gt * Gc[d] + gb[d];
+        for (int d = 0; d < D; ++d) grad_force[(long long)d * P.nc + cidx] += gt * Gc[d] + gin[(long long)d * P.nc + cidx];
 }
 
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
@@ -945,7 +991,8 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
                         + nwall * (Q + D) * es       // NEQ parts of the opposite interfaces
                         + (size_t)P.ne * Q * es      // phi_hat (extended)
                         + (size_t)D * P.ne * Q * es  // d_hat (extended)
-                        + (size_t)P.ne * D * es;     // force adjoint (extended)
+                        + (size_t)P.ne * D * es      // force adjoint (extended)
+                        + (size_t)P.nc * (Q + D) * es; // phi_hat and force adjoint gathered per cell
     if (ctx->adj_bytes < need) {
         if (ctx->adj) (void)hipFree(ctx->adj);
         ctx->adj = nullptr;
@@ -986,6 +1033,10 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
     T* dhat = p;
     p += (size_t)D * P.ne * Q;
     T* gext = p;
+    p += (size_t)P.ne * D;
+    T* pin = p;
+    p += (size_t)P.nc * Q;
+    T* gin = p;
     const Inst<T>* Pd = (const Inst<T>*)ctx->inst_dev;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
     const T* lam = (const T*)lam_np1;
@@ -995,9 +1046,12 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
                        phi, gt);
     hipLaunchKernelGGL((k_adjw_face<LAT, T>), dim3(nb256(maxf), D), dim3(256), 0, st, Pd, (const T*)phi,
                        (const T*)force, lam, gth, AF);
-    hipLaunchKernelGGL((k_adjw_psi<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, AF, lam, gth, php, dhat, gext);
+    hipLaunchKernelGGL((k_adjw_psi<LAT, T>), dim3(nb256(P.ne), Q), dim3(256), 0, st, Pd, AF, lam, gth, php, dhat,
+                       gext);
+    hipLaunchKernelGGL((k_adjw_gather<LAT, T>), dim3(nb256(P.nc), Q), dim3(256), 0, st, Pd, (const T*)php,
+                       (const T*)dhat, (const T*)gext, pin, gin);
     hipLaunchKernelGGL((k_adjw_cell<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)fn, (const T*)force,
-                       lam, (const T*)php, (const T*)dhat, (const T*)gext, gt, (T*)lam_n, (T*)grad_force);
+                       lam, (const T*)pin, (const T*)gin, gt, (T*)lam_n, (T*)grad_force);
     return hip_check(ctx, hipGetLastError(), "adjoint (walls) launch");
 }
 
