@@ -261,3 +261,33 @@ def test_force_field_gradient_matches_fd():
             Gp[ix] = eps
             fd = (loss_of(Gp) - loss_of(-Gp)).item() / (2 * eps)
         assert grad[ix] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(grad).max())
+
+
+F32_CASES = [("q9-periodic", 9, (37, 29), (0,) * 6, 0, LID, (0,) * 6), WALL_CASES[0], WALL_CASES[3], WALL_CASES[7]]
+
+
+@pytest.mark.parametrize("name,lat,n,bc,mesh,uw,pw", F32_CASES, ids=[c[0] for c in F32_CASES])
+def test_step_adjoint_f32_against_oracle(name, lat, n, bc, mesh, uw, pw):
+    # FP32 reverse pass against the FP64 oracle: the adjoint of one step is
+    # a sum of O(10) terms of O(1) per entry, so FP32 rounding stays near
+    # 1e-6 of the largest entry; 2e-5 is the FP32 gate of the forward path
+    say(f"[adjoint f32] {name}")
+    cfg = periodic_cfg(lat, n, mesh, bc=bc, uw=uw, pw=list(pw))
+    Q, D, shp = M.shape_of(cfg)
+    Gf = field(51, (D,) + shp, 2e-3)
+    f = perturb(52, O.init(cfg, rho=1 + field(53, shp, 0.02), u=field(54, (D,) + shp, 0.05), force=Gf), 1e-2)
+    lam = field(55, f.shape, 1.0)
+    gref = np.zeros_like(Gf)
+    ref = O.step_adjoint(cfg, f, lam, force=Gf, t=0.4, grad_force=gref)
+    c32 = dict(cfg, dtype="f32")
+    buf = torch.empty((Q,) + shp, dtype=torch.float32, device="cuda")
+    ctx = M.dugks_init(c32, buf)
+    try:
+        out = torch.empty_like(buf)
+        gG = torch.zeros((D,) + shp, dtype=torch.float32, device="cuda")
+        M.dugks_step_adjoint(ctx, dev(f).float(), dev(lam).float(), out, dev(Gf).float(), 0.4, gG)
+        torch.cuda.synchronize()
+        assert np.abs(out.double().cpu().numpy() - ref).max() / np.abs(ref).max() < 2e-5
+        assert np.abs(gG.double().cpu().numpy() - gref).max() / np.abs(gref).max() < 2e-5
+    finally:
+        M.dugks_destroy(ctx)
