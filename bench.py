@@ -26,6 +26,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
        [--mesh uniform|tanh] [--re 100] [--n 128] [--no-cpu-baseline]
        [--no-extras]
        python bench.py --cavity-re12000   (the unsteady 2-D cavity of Sec. III)
+       python bench.py --adjoint-only     (adjoint vs forward step, periodic and walled 256^2)
        python bench.py --summarize-counters FETCH_DIR WRITE_DIR
          (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output of
           `bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras
@@ -403,6 +404,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter scaling)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="print only the adjoint figures (periodic and walled D2Q9 256^2) as one JSON line")
     ap.add_argument("--cavity-re12000", action="store_true",
                     help="run the Re = 12000 2-D cavity (128^2 to t = 3000, 96^2 and 80^2 to t = 1500; "
                          "about five minutes) and print its JSON line instead of the benchmark")
@@ -425,6 +428,9 @@ def main():
     torch.cuda.init()
     if args.cavity_re12000:
         print(json.dumps(bench_cavity12000()))
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint(), "adjoint_walls": bench_adjoint(walls=True)}))
         return
     cfg = cavity_cfg(args.n, args.dtype, args.mesh, args.re)
     Q, D, shp = M.shape_of(cfg)
