@@ -417,7 +417,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the step is measured on one MI355X); "
+        print("bench.py: the benchmark runs on one GPU only (the step is measured on one MI355X); "
               "multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 

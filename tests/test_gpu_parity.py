@@ -1,6 +1,6 @@
 """HIP path vs the CPU oracle, through the C ABI, on the same seeded inputs.
 
-Tolerances (spec accuracy gates): FP64 state 1e-12 relative L-inf per
+Tolerances (accuracy gates): FP64 state 1e-12 relative L-inf per
 step and 1e-10 after 10^4 steps; FP32 velocity within 2e-5 of the velocity
 scale.  Sizes span several kernel tiles with ragged tails; walls of every
 kind, both meshes, both lattices, forcing with a time factor.
