@@ -117,3 +117,72 @@ def test_full_batch_equals_plain_launches(dtype):
                 M.dugks_destroy(ctx)
     finally:
         B.close()
+
+
+@pytest.mark.parametrize("bc", [3, 1], ids=["bounce-back", "neq"])
+def test_channel_workload_20000_steps(bc):
+    # the force-driven periodic channel: 4 x 32 cells, periodic in x, walls
+    # in y, rho0 = 1, RT = 1/3, tau = 0.1 (nu = tau RT), dt from CFL 0.5,
+    # G for u_max = 0.01, from rest, 20000 steps; GPU vs oracle and both
+    # against the parabola (at this tau the walls slip by O(tau): a few %)
+    from tests.test_oracle_flows import channel
+
+    nu = 0.1 / 3
+    d, y = channel(32, bc, 1 / 3, nu=nu, G=8 * nu * 0.01, nx=4)
+    d["dtype"] = "f64"
+    say(f"[full size] channel 4x32 bc={bc}, 20000 steps")
+    oc = {k: v for k, v in d.items() if k != "dtype"}
+    f0 = O.init(oc)
+    ref = O.run(oc, f0, 20000)
+    got = gpu_steps(d, f0, 20000)
+    assert rel_linf(got, ref) < 1e-10
+    ua = d["G"][0] / (2 * nu) * y * (1 - y)
+    _, u, _, _ = O.moments(oc, got)
+    err = np.sqrt(((u[0, 0, :, 0] - ua) ** 2).sum() / (ua ** 2).sum())
+    assert err < 0.1
+
+
+def test_womersley_channel_32x256():
+    # Womersley channel, 32 x 256 cells (periodic x), bounce-back walls,
+    # oscillating force G cos(omega t) at Womersley number 4 (alpha^2 =
+    # Ly^2 omega / (4 nu)), continuum regime (RT = 1000/3): parity with the
+    # oracle over 200 steps, then one period on the GPU from the analytic
+    # state against the closed form at eight phases of the next period
+    from tests.test_oracle_flows import RT_C, channel, womersley_u
+
+    nu, alpha, G = 0.01, 4.0, 1e-3
+    omega = 4 * alpha ** 2 * nu
+    d, y = channel(256, 3, RT_C, nu=nu, G=G, nx=32)
+    T = 2 * np.pi / omega
+    nper = int(round(T / d["dt"]))
+    nper -= nper % 8
+    d["dt"] = T / nper
+    d["omega"] = omega
+    d["dtype"] = "f64"
+    say(f"[full size] Womersley 32x256, alpha 4, {nper} steps per period")
+    oc = {k: v for k, v in d.items() if k != "dtype"}
+    Q, D, shp = M.shape_of(d)
+    u0 = np.zeros((2,) + shp)
+    u0[0] = womersley_u(y, 0.0, G, omega, nu)[None, :, None]
+    f0 = O.init(oc, u=u0)
+    ref = O.run(oc, f0, 200)
+    assert rel_linf(gpu_steps(d, f0, 200), ref) < 1e-12
+    fa = torch.from_numpy(f0).to("cuda")
+    fb = torch.empty_like(fa)
+    ctx = M.dugks_init(d, fb)
+    try:
+        t, worst = 0.0, 0.0
+        cur, nxt = fa, fb
+        u = torch.empty((2,) + shp, dtype=torch.float64, device="cuda")
+        for k in range(16):
+            if M.dugks_run(ctx, cur, nxt, nper // 8, None, t):
+                cur, nxt = nxt, cur
+            t += (nper // 8) * d["dt"]
+            if k >= 8:
+                M.dugks_moments(ctx, cur, t=t, u=u)
+                ux = u[0, 0, :, 0].cpu().numpy()
+                worst = max(worst, np.abs(ux - womersley_u(y, t, G, omega, nu)).max() / (G / omega))
+    finally:
+        M.dugks_destroy(ctx)
+    say(f"[full size] Womersley worst error {worst:.2e} of G/omega")
+    assert worst < 1e-2
