@@ -91,8 +91,10 @@ enum dugks_bc {
  *   bc[6]       side kinds; uw[6][3] wall velocities; pw[6] wall pressures
  *               (pressure p = (rho - rho0) RT)
  *   model       DUGKS_MODEL_INCOMPRESSIBLE (0, the paper's model) or
- *               DUGKS_MODEL_ORIGINAL (1: runs on the general kernels; no
- *               batched form, no adjoint: DUGKS_EUNSUPPORTED there)
+ *               DUGKS_MODEL_ORIGINAL (1: the two-lane fused kernel where the
+ *               incompressible model would take it and no force field is
+ *               given, else the general kernels; no batched form, no
+ *               adjoint: DUGKS_EUNSUPPORTED there)
  * D3Q27 has no batched form and no adjoint (DUGKS_EUNSUPPORTED).
  */
 typedef struct {

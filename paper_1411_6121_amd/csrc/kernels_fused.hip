@@ -648,7 +648,16 @@ int setup_fast(dugks_ctx* ctx)
 // the step kernel a launch with (without) a force field uses
 int resolve_step_kernel(const dugks_ctx* ctx, bool field)
 {
-    if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) return 0;
+    // the original-model variant: the two-lane kernel where it is the
+    // incompressible choice and no force field is given, else the general
+    // kernels
+    if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) {
+        if (field || ctx->fast == 0) return 0;
+        if (ctx->cfg.lattice == DUGKS_D3Q27) return 3;
+        const bool uni = ctx->cfg.dtype == DUGKS_F64 ? ctx->pd.uni != 0 : ctx->pf.uni != 0;
+        const int v = ctx->fast != 4 ? ctx->fast : default_step_kernel(ctx->cfg.lattice, ctx->cfg.dtype, uni, false);
+        return v == 3 ? 3 : 0;
+    }
     // D3Q27 has the split kernel only (the one-lane tile would not fit a CU)
     if (ctx->cfg.lattice == DUGKS_D3Q27) return ctx->fast == 0 ? 0 : 3;
     if (ctx->fast != 4) return ctx->fast;
@@ -659,8 +668,6 @@ int resolve_step_kernel(const dugks_ctx* ctx, bool field)
 int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, bool* handled)
 {
     *handled = false;
-    // the original-model variant runs on the general two-kernel path
-    if (ctx->cfg.model != DUGKS_MODEL_INCOMPRESSIBLE) return DUGKS_OK;
     const int variant = resolve_step_kernel(ctx, force != nullptr);
     if (variant < 1 || variant > 3) return DUGKS_OK;
     *handled = true;

@@ -93,7 +93,7 @@ struct HalfPhi {
 
 // cell moments and f-bar-plus (Appendix step 1, Eq. f_bar_+) of the lane's
 // velocities; fv: lane velocities, fr: rest velocity (both lanes hold it)
-template <class LAT, typename T, bool NOG = false>
+template <class LAT, typename T, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::REST], T fr, const T (&fg)[3],
                                          bool has_field, T gt, T sg, T (&out)[LAT::REST], T& orest)
 {
@@ -115,19 +115,19 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
         const T jh = sg * sj[a];
         const T j = jh + partner(jh);
         if constexpr (NOG) {
-            u[a] = P.crho * j;
+            u[a] = ORIG ? P.c * j / rho : P.crho * j;
         } else {
             G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
-            u[a] = P.crho * j + P.h * G[a];
+            u[a] = vel_from<T, ORIG>(P, rho, j, G[a], P.h);
         }
         us[a] = sg * u[a];
         Gs[a] = sg * G[a];
     }
     // NOG: no acceleration at all, the source term of Eq. (S) vanishes
-    const EqPt<T> E = eq_point<LAT, T>(P, rho, us, NOG ? nullptr : Gs);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const T fe = feq_pt<LAT, T>(P, E, k);
+        const T fe = feq_pt<LAT, T, ORIG>(P, E, k);
         if constexpr (NOG) {
             out[k] = fv[k] + P.B1 * (fe - fv[k]);
         } else {
@@ -135,7 +135,7 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
             out[k] = fv[k] + P.B1 * (fe - fv[k]) + P.C1 * S;
         }
     }
-    const T fe = feq_pt<LAT, T>(P, E, LAT::REST);
+    const T fe = feq_pt<LAT, T, ORIG>(P, E, LAT::REST);
     if constexpr (NOG) {
         orest = fr + P.B1 * (fe - fr);
     } else {
@@ -187,7 +187,7 @@ __device__ __forceinline__ void recon_half(const Inst<T>& P, const ACC& ph, int 
 }
 
 // interface moments (Appendix step 6) from the two lanes' values
-template <class LAT, typename T, bool NOG = false>
+template <class LAT, typename T, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
                                              T& rho, T* u)
 {
@@ -206,8 +206,9 @@ __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const T jh = sg * sj[a];
-        if constexpr (NOG) u[a] = P.crho * (jh + partner(jh));
-        else u[a] = P.crho * (jh + partner(jh)) + T(0.5) * P.h * G[a];
+        const T j = jh + partner(jh);
+        if constexpr (NOG) u[a] = ORIG ? P.c * j / rho : P.crho * j;
+        else u[a] = vel_from<T, ORIG>(P, rho, j, G[a], T(0.5) * P.h);
     }
 #pragma unroll
     for (int a = D; a < 3; ++a) u[a] = T(0);
@@ -220,25 +221,25 @@ struct NeqHalf {
     T neq[LAT::REST];
 };
 
-template <class LAT, typename T, int A, bool NOG = false>
+template <class LAT, typename T, int A, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void neq_capture_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
                                                  NeqHalf<LAT, T>& I)
 {
-    moments_half<LAT, T, NOG>(P, fb, fr, G, sg, I.rc, I.uc);
+    moments_half<LAT, T, NOG, ORIG>(P, fb, fr, G, sg, I.rc, I.uc);
     T us[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < LAT::D; ++a) us[a] = sg * I.uc[a];
-    const EqPt<T> E = eq_point<LAT, T>(P, I.rc, us, nullptr);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, I.rc, us, nullptr);
 #pragma unroll
     for (int k = 0; k < LAT::REST; ++k) {
         if (LAT::e(k, A) == 0) continue;
-        I.neq[k] = fb[k] - feq_pt<LAT, T>(P, E, k);
+        I.neq[k] = fb[k] - feq_pt<LAT, T, ORIG>(P, E, k);
     }
 }
 
 // Appendix step 5 on a wall face of side s = 2A + (sgs > 0) (Eqs. BB, NEQ)
 // for the lane's velocities entering the domain (sigma e_A sgs < 0)
-template <class LAT, typename T, int A>
+template <class LAT, typename T, int A, bool ORIG = false>
 __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&wall)[LAT::REST],
                                           const NeqHalf<LAT, T>& I, T sg, int sgi)
 {
@@ -270,19 +271,19 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = sg * I.uc[d];
     }
-    const EqPt<T> E = eq_point<LAT, T>(P, ra, ua, nullptr);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, ra, ua, nullptr);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (LAT::e(k, A) == 0) continue;
         if (sgi * LAT::e(k, A) * sgs >= 0) continue;
-        wall[k] = feq_pt<LAT, T>(P, E, k) + I.neq[k];
+        wall[k] = feq_pt<LAT, T, ORIG>(P, E, k) + I.neq[k];
     }
 }
 
 // The interface of axis A with index f between the cells at offsets off and
 // off+1: steps 3-7 for the lane's velocities; out[half_cross_slot] receives
 // f (step 7) of the lane's velocities crossing the face.
-template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false>
+template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
                                           int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
                                           const CellMetric<T>& mz, T sg, int sgi, T* out)
@@ -301,28 +302,28 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
         const T wo = UNI ? T(0.5) : m.w[fo];
         recon_half<LAT, T, ACC, A, UNI>(P, ph, oo, wo, UNI ? P.ugn[A] : m.gn[fo], mx, my, mz, sg, fb, fr);
         if constexpr (!NOG) face_force<LAT, T>(P, force, A, fo, wo, ci, gth, G);
-        neq_capture_half<LAT, T, A, NOG>(P, fb, fr, G, sg, info);
+        neq_capture_half<LAT, T, A, NOG, ORIG>(P, fb, fr, G, sg, info);
         asm volatile("" ::: "memory");
     }
     const T w = UNI ? T(0.5) : m.w[f];
     recon_half<LAT, T, ACC, A, UNI>(P, ph, off, w, UNI ? P.ugn[A] : m.gn[f], mx, my, mz, sg, fb, fr);
     if constexpr (NOG) G[0] = G[1] = G[2] = T(0);
     else face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
-    if (wall_lo) wall_half<LAT, T, A>(P, 2 * A, -1, fb, info, sg, sgi);
-    if (wall_hi) wall_half<LAT, T, A>(P, 2 * A + 1, 1, fb, info, sg, sgi);
+    if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi);
+    if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi);
     T rho, u[3];
-    moments_half<LAT, T, NOG>(P, fb, fr, G, sg, rho, u);
+    moments_half<LAT, T, NOG, ORIG>(P, fb, fr, G, sg, rho, u);
     T us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < LAT::D; ++a) {
         us[a] = sg * u[a];
         Gs[a] = sg * G[a];
     }
-    const EqPt<T> E = eq_point<LAT, T>(P, rho, us, NOG ? nullptr : Gs);
+    const EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (LAT::e(k, A) == 0) continue;
-        const T fe = feq_pt<LAT, T>(P, E, k);
+        const T fe = feq_pt<LAT, T, ORIG>(P, E, k);
         if constexpr (NOG) {
             out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]);  // step 7 without a source
         } else {
@@ -350,7 +351,7 @@ constexpr bool own_regs()
     return LAT::Q == 9 || (LAT::Q == 19 && UNI && !FF);
 }
 
-template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN, bool NOG = false>
+template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                            T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                            int ck, T* lds)
@@ -445,7 +446,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     auto compute_plane = [&](int p) {
         if (cell_col) {
             T v[K], vr;
-            phi_half<LAT, T, NOG>(P, pf, prest, pg, force != nullptr, gt, sg, v, vr);
+            phi_half<LAT, T, NOG, ORIG>(P, pf, prest, pg, force != nullptr, gt, sg, v, vr);
 #pragma unroll
             for (int k = 0; k < K; ++k) lds[lds_el(p, hs + k, 0, 0)] = v[k];
             if (h == 0) lds[lds_el(p, K, 0, 0)] = vr;
@@ -531,8 +532,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         ci[2] = (D == 3) ? p0 : 0;
         const CellMetric<T> cmm = load_metric(P, M, p0);
         const auto ph = phi_view(p0);
-        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
-        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
+        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
+        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
     }
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
@@ -578,22 +579,22 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         T zhi[NM > 0 ? NM : 1];
         if (xface) {
             T v[NX];
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
 #pragma unroll
             for (int kc = 0; kc < NX; ++kc) fxb[((h * NX + kc) * BY + ty) * BX + tx] = v[kc];
         }
         if constexpr (D == 3) {
             if (yface) {
                 T v[NY];
-                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI, NOG>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI, NOG, ORIG>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
 #pragma unroll
                 for (int kc = 0; kc < NY; ++kc) fyb[((h * NY + kc) * BY + ty) * BX + tx] = v[kc];
             }
         }
         if (upd_col) {
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
         }
         __syncthreads();
         if (upd_col) {
@@ -639,7 +640,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
 
 // FF: the launch carries a force field (without one the kernel is compiled
 // with a null field and no field code)
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI, bool NOG>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI, bool NOG, bool ORIG = false>
 __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_eu<LAT, T, true>())) void k_split(const Inst<T>* __restrict__ Pp,
                                                                           const T* __restrict__ fin,
                                                                           const T* __restrict__ force,
@@ -650,7 +651,7 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const Inst<T>& P = *Pp;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    split_body<LAT, T, BX, BY, PF, UNI, own_regs<LAT, T, UNI, FF>(), NOG>(P, fin, FF ? force : nullptr, fout, gt, gth,
+    split_body<LAT, T, BX, BY, PF, UNI, own_regs<LAT, T, UNI, FF>(), NOG, ORIG>(P, fin, FF ? force : nullptr, fout, gt, gth,
                                                                          chunk,
                                                                     tiles0, b % tiles, b / tiles,
                                    reinterpret_cast<T*>(smem_raw));
@@ -700,7 +701,7 @@ static size_t split_lds()
            BX * BY * sizeof(T);
 }
 
-template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI, bool NOG = false>
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI, bool NOG = false, bool ORIG = false>
 static int launch_split_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void* fout, const void* force, double t,
                            hipStream_t st, int chunk)
 {
@@ -708,7 +709,7 @@ static int launch_split_ff(dugks_ctx* ctx, const Inst<T>& P, const void* fin, vo
     const int tiles0 = (P.n[0] + BX - 3) / (BX - 2);
     const int tiles1 = (D == 3) ? (P.n[1] + BY - 3) / (BY - 2) : 1;
     const size_t lds = split_lds<LAT, T, BX, BY>();
-    auto kern = k_split<LAT, T, BX, BY, MINW, PF, FF, UNI, NOG>;
+    auto kern = k_split<LAT, T, BX, BY, MINW, PF, FF, UNI, NOG, ORIG>;
     static bool attr_set = false;
     static long long slots = 0;
     if (!attr_set) {
@@ -737,6 +738,11 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     // no acceleration at all (G = 0, no field): instances without the
     // source term of Eq. (S) (bitwise the same results, fewer operations)
     const bool nog = !force && P.G0[0] == T(0) && P.G0[1] == T(0) && P.G0[2] == T(0);
+    if (P.orig) {
+        // the original-model equilibrium (launches without a force field)
+        if (P.uni) return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+        return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, false, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+    }
     if (P.uni) {
         if (force) return launch_split_ff<LAT, T, BX, BY, MINW, PF, true, true>(ctx, P, fin, fout, force, t, st, chunk);
         if (nog) return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true, true>(ctx, P, fin, fout, force, t, st, chunk);

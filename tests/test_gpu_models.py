@@ -1,12 +1,13 @@
 """The original-DUGKS equilibrium variant (model = 1) on the GPU against the
-oracle: one step and 30 steps (FP64), initial state and moments, FP32
-velocity; the paths that do not support it refuse it."""
+oracle: one step and 30 steps (FP64) on the two-lane kernel (launches
+without a force field) and on the general kernels, initial state and
+moments, FP32 velocity; the paths that do not support it refuse it."""
 import numpy as np
 import pytest
 
 import oracle as O
 from synthetic import field, perturb
-from tests.test_gpu_parity import LID, LID3, c2, c3, gpu_run, rel_linf, tdt, to_dev
+from tests.test_gpu_parity import LID, LID3, c2, c3, default_kernel, gpu_run, rel_linf, tdt, to_dev
 
 torch = pytest.importorskip("torch")
 M = pytest.importorskip("paper_1411_6121_amd")
@@ -29,15 +30,23 @@ CASES = [
 ]
 
 
+CASES += [
+    c3("orig-d3q27-cavity-neq", (12, 10, 9), (1,) * 6, uw=LID3, lattice=27, model=1),
+    c2("orig-d2q9-moving-bb-force", (30, 22), (3, 3, 3, 3, 0, 0), G=(2e-4, 1e-4, 0),
+       uw=[[0, 0.02, 0], [0, -0.01, 0], [0.03, 0, 0], [0.05, 0, 0], [0, 0, 0], [0, 0, 0]], model=1),
+]
+
+
+@pytest.mark.parametrize("variant", [None, "general"], ids=["default", "general"])
 @pytest.mark.parametrize("cfg", CASES, ids=[c["name"] for c in CASES])
-def test_original_model_step_parity(cfg):
-    say(f"[original model] {cfg['name']} n={cfg['n']}")
+def test_original_model_step_parity(cfg, variant):
+    say(f"[original model] {cfg['name']} n={cfg['n']} {variant or 'default'}")
     Q, D, shp = M.shape_of(cfg)
     force = field(5, (D,) + shp, 1e-4) if cfg.get("force_field") else None
     f0 = perturb(13, O.init(cfg, rho=1.0 + field(11, shp, 0.01), u=field(12, (D,) + shp, 0.03), force=force), 1e-3)
     t0 = 0.7
-    assert rel_linf(gpu_run(cfg, f0, 1, force, t0), O.step(cfg, f0, force, t0)) < 1e-12
-    assert rel_linf(gpu_run(cfg, f0, 30, force, t0), O.run(cfg, f0, 30, force, t0)) < 1e-11
+    assert rel_linf(gpu_run(cfg, f0, 1, force, t0, variant), O.step(cfg, f0, force, t0)) < 1e-12
+    assert rel_linf(gpu_run(cfg, f0, 30, force, t0, variant), O.run(cfg, f0, 30, force, t0)) < 1e-11
 
 
 @pytest.mark.parametrize("lat", [9, 19])
@@ -53,7 +62,7 @@ def test_original_model_init_and_moments(lat):
     f = torch.empty((Q,) + shp, dtype=tdt(cfg), device="cuda")
     ctx = M.dugks_init(cfg, f, to_dev(rho, cfg), to_dev(u, cfg), to_dev(force, cfg))
     try:
-        assert M.dugks_kernel_variant(ctx) == 0  # the general kernels
+        assert M.dugks_kernel_variant(ctx) == default_kernel(cfg)
         assert rel_linf(f.cpu().numpy(), ref) < 1e-14
         fs = perturb(4, ref, 1e-3)
         r_ref, u_ref, p_ref, tot_ref = O.moments(cfg, fs, force, 0.4)

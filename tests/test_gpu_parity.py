@@ -39,14 +39,15 @@ VARIANTS = {"general": 0, "fused-twice": 1, "fused": 2, "split": 3}
 
 def default_kernel(cfg):
     """the library's default step kernel for a launch without a force field
-    (documented in dugks.h)"""
-    if cfg.get("model", 0) == 1:
-        return 0  # the original-model variant runs on the general kernels
+    (documented in dugks.h); the original-model variant takes the two-lane
+    kernel where the incompressible model would, else the general kernels"""
     if cfg["lattice"] == 27:
         return 3
     if cfg["lattice"] == 9 or cfg.get("dtype", "f64") == "f64":
         return 3
     uniform = all(m == 0 for m in cfg.get("mesh", (0, 0, 0)))
+    if cfg.get("model", 0) == 1:
+        return 3 if uniform else 0
     return 3 if uniform else 2
 
 
