@@ -248,7 +248,8 @@ int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, 
  * over two lanes per column.  By default each launch takes the faster one
  * on MI355X: 3 for D2Q9 and D3Q27, for D3Q19 FP64 without a force field
  * and for D3Q19 FP32 on uniform meshes without one; 2 otherwise.  The
- * original-model variant always uses 0.  A batch decides
+ * original-model variant uses 3 where the incompressible model would and
+ * no force field is given, else 0.  A batch decides
  * once for all its instances (uniform meshes, any force field), so batched
  * and single-instance states are bitwise equal when the instances share
  * the mesh kind and the presence of a force field.  All kernels give the
