@@ -1,7 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times: the D3Q19 128^3 cavity (uniform and tanh meshes, FP64 and
 FP32), the D2Q9 1024^2 cavity, the 2-D Re = 12000 cavity (128^2 tanh
-mesh, bounce-back walls) and the 64-instance uneven batch.
+mesh, bounce-back walls), the 4 x 32 channel over 20000 steps, the 32 x 256
+Womersley channel, the 64-instance uneven batch, and a 640^3 periodic mesh
+(5e9 state elements, past 32-bit offsets) checked block by block.
 
 Whole-field comparisons: one oracle step at these sizes takes well under a
 second on the host cores, so every output value is checked, not a sample.
@@ -186,3 +188,42 @@ def test_womersley_channel_32x256():
         M.dugks_destroy(ctx)
     say(f"[full size] Womersley worst error {worst:.2e} of G/omega")
     assert worst < 1e-2
+
+
+@pytest.mark.parametrize("G", [(0.0, 0.0, 0.0), (2e-5, -1e-5, 1e-5)], ids=["no-acceleration", "forced"])
+def test_large_periodic_mesh_64bit_offsets(G):
+    # 640^3 D3Q19 FP64 (19 x 640^3 = 5.0e9 state elements, beyond 32-bit
+    # offsets): a periodic state that repeats a seeded 10^3 block stays
+    # periodic, so after two steps every 10^3 block must equal the oracle's
+    # two steps of the 10^3 periodic mesh
+    n, p = 640, 10
+    small = c3_periodic(p, G)
+    big = dict(small, n=(n, n, n), L=(float(n),) * 3)
+    say(f"[full size] D3Q19 {n}^3 periodic from a tiled {p}^3 block, G={G}")
+    f0 = flow_state(small, 67)
+    ref = torch.from_numpy(O.run(small, f0, 2)).to("cuda")
+    r = n // p
+    fa = torch.from_numpy(f0).to("cuda").repeat(1, r, r, r)
+    fb = torch.empty_like(fa)
+    ctx = M.dugks_init(big, fb)
+    try:
+        assert M.dugks_kernel_variant(ctx) == default_kernel(big)
+        which = M.dugks_run(ctx, fa, fb, 2, None, 0.0)
+        got = fb if which else fa
+        worst = 0.0
+        scale = ref.abs().max().item()
+        for z0 in range(0, n, 80):  # compare slab by slab (bounded temporaries)
+            sl = got[:, z0:z0 + 80].reshape(19, 80 // p, p, r, p, r, p)
+            d = (sl - ref.reshape(19, 1, p, 1, p, 1, p)).abs().max().item()
+            worst = max(worst, d)
+        torch.cuda.synchronize()
+    finally:
+        M.dugks_destroy(ctx)
+        del fa, fb
+        torch.cuda.empty_cache()
+    assert worst / scale < 1e-12
+
+
+def c3_periodic(p, G):
+    return dict(lattice=19, dtype="f64", n=(p, p, p), L=(float(p),) * 3, rho0=1.0, RT=1 / 3, tau=0.3, dt=0.5,
+                bc=(0,) * 6, G=G)
