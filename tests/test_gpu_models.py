@@ -88,3 +88,55 @@ def test_original_model_f32_velocity():
     _, u_ref, _, _ = O.moments(cfg, ref)
     _, u_got, _, _ = O.moments(cfg, got)
     assert np.abs(u_got - u_ref).max() / 0.1 < 2e-5
+
+
+def test_compressibility_comparison_on_the_gpu():
+    # Sec. III.A: the force-driven periodic flow at Ma = 0.0152 and 0.1216
+    # with both models, run on the GPU (the same recipe as the oracle's pin:
+    # 32^2, nu = 0.01, dt = 1e-4, CFL 0.1, t = 4 from the analytic state);
+    # the error growth and the reduction at the highest Mach number are
+    # checked against the printed values, and a short run of each model
+    # against the oracle
+    import os
+
+    from tests.test_oracle_models import GOLDEN
+
+    with open(os.path.join(GOLDEN, "compressibility_periodic_flow.txt")) as fh:
+        ref = dict(ln.split() for ln in fh if ln.strip() and not ln.startswith("#"))
+
+    def setup(model, Ma, N=32, nu=0.01, dt=1e-4, cfl=0.1):
+        c = cfl / N / dt
+        RT = c * c / 3
+        u0 = Ma * c
+        d = dict(lattice=9, dtype="f64", n=(N, N, 1), L=(1.0, 1.0, 1.0), rho0=1.0, RT=RT, tau=nu / RT, dt=dt,
+                 bc=(0,) * 6, model=model)
+        _, xc = O.mesh(d, 0)
+        X, Y = np.meshgrid(xc[1:-1], xc[1:-1], indexing="xy")
+        ua = np.stack([u0 * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y),
+                       u0 * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Y)])[:, None]
+        pa = 0.25 * u0 ** 2 * (np.cos(4 * np.pi * X) - np.cos(4 * np.pi * Y))[None]
+        F = 8 * np.pi ** 2 * nu * ua
+        return d, ua, F, O.init(d, rho=1.0 + pa / RT, u=ua, force=F)
+
+    def gpu_error(model, Ma, T=4.0):
+        d, ua, F, f0 = setup(model, Ma)
+        nsteps = int(round(T / d["dt"]))
+        got = gpu_run(d, f0, nsteps, F, 0.0)
+        _, u, _, _ = O.moments(d, got, force=F)
+        return np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum())
+
+    say("[original model] compressibility comparison on the GPU")
+    for model in (0, 1):
+        d, ua, F, f0 = setup(model, 0.1216)
+        assert rel_linf(gpu_run(d, f0, 300, F, 0.0), O.run(d, f0, 300, F, 0.0)) < 1e-11
+    lo, hi = 0.0152, 0.1216
+    ec = [gpu_error(1, m) for m in (lo, hi)]
+    ei = [gpu_error(0, m) for m in (lo, hi)]
+    say(f"  errors original {ec}, incompressible {ei}")
+    growth_c = ec[1] / ec[0] - 1
+    growth_i = ei[1] / ei[0] - 1
+    reduction = 1 - ei[1] / ec[1]
+    assert growth_c == pytest.approx(float(ref["growth_original"]), abs=0.06)
+    assert 0 <= growth_i < 2 * float(ref["growth_incompressible"])
+    assert reduction == pytest.approx(float(ref["reduction_at_max"]), abs=0.04)
+    assert ec[0] == pytest.approx(ei[0], rel=1e-3)
