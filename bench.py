@@ -213,7 +213,7 @@ def bench_batched(dtype="f64", count=64, steps=100, warmup=5):
             "accuracy": "bitwise identical to the plain launches"}
 
 
-def bench_adjoint(n=256, steps=50, warmup=5, walls=False):
+def bench_adjoint(n=256, steps=50, warmup=5, walls=False, full_steps=2000):
     """adjoint step vs forward step, D2Q9 n^2, FP64, tau = 1, with a
     body-force field (the gradient workload): periodic, or (walls) a
     lid-driven cavity with NEQ walls on a tanh mesh (k = 1.5)"""
@@ -253,8 +253,46 @@ def bench_adjoint(n=256, steps=50, warmup=5, walls=False):
     finally:
         M.dugks_destroy(ctx)
     kind = "lid-driven cavity, NEQ walls, tanh mesh" if walls else "periodic"
-    return {"workload": f"D2Q9 {n}^2 {kind}, force field, f64", "ms_forward_step": round(ms_f, 4),
-            "ms_adjoint_step": round(ms_a, 4), "ratio": round(ms_a / ms_f, 3)}
+    out = {"workload": f"D2Q9 {n}^2 {kind}, force field, f64", "ms_forward_step": round(ms_f, 4),
+           "ms_adjoint_step": round(ms_a, 4), "ratio": round(ms_a / ms_f, 3)}
+    if not walls and full_steps > 0:
+        out["full_gradient"] = full_gradient_time(cfg, Gf, full_steps, ms_f)
+    return out
+
+
+def full_gradient_time(cfg, Gtar, nsteps, ms_forward):
+    """Wall time of one whole gradient (checkpointed forward, recompute and
+    adjoint steps, initial-state and read-out VJPs, host calls included) of
+    the MSE between the final velocity at zero force and at Gtar, in units
+    of plain forward steps"""
+    import math
+    import time
+
+    import torch
+
+    import paper_1411_6121_amd as M
+    from paper_1411_6121_amd.autograd import rollout
+
+    Q, D, shp = M.shape_of(cfg)
+    zero_u = torch.zeros((D,) + shp, dtype=torch.float64, device="cuda")
+    with torch.no_grad():
+        u_tar = rollout(cfg, Gtar, zero_u, nsteps)
+
+    def grad_once():
+        G = torch.zeros((D,) + shp, dtype=torch.float64, device="cuda", requires_grad=True)
+        ((rollout(cfg, G, zero_u, nsteps) - u_tar) ** 2).mean().backward()
+        return G.grad
+
+    grad_once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = grad_once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    if not bool(torch.isfinite(g).all()):
+        raise SystemExit("non-finite gradient")
+    return {"steps": nsteps, "checkpoints": math.ceil(math.sqrt(nsteps)), "ms": round(ms, 2),
+            "forward_step_units": round(ms / (nsteps * ms_forward), 2)}
 
 
 def summarize_counters(fetch_dir, write_dir, workload):

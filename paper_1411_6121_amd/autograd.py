@@ -4,7 +4,8 @@ with sqrt(N) checkpointing (Griewank-style two-level recomputation).
 
 Memory: ceil(sqrt(N)) checkpoint states plus one segment of at most
 ceil(sqrt(N)) states during the backward pass; compute: one extra forward
-pass.  Periodic meshes only (the adjoint step's domain).
+pass.  Any mesh and boundary set of the incompressible model (those of the
+adjoint step).
 """
 from __future__ import annotations
 
