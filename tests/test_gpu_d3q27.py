@@ -32,6 +32,9 @@ CASES = [
     q27("d3q27-mixed", (12, 9, 11), (2, 2, 1, 3, 0, 0), pw=[2e-3, 0, 0, 0, 0, 0], uw=LID3, mesh=(0, 1, 0),
         k_stretch=1.2, dt=0.3),
     q27("d3q27-original-model", (10, 9, 8), (1,) * 6, uw=LID3, model=1),
+    q27("d3q27-minimal", (2, 2, 2), (1, 1, 3, 3, 1, 1), uw=LID3),
+    q27("d3q27-one-plane-periodic-z", (7, 6, 1), (1, 1, 1, 1, 0, 0), uw=LID3),
+    q27("d3q27-one-column-periodic-x", (1, 5, 4), (0, 0, 3, 3, 1, 1), uw=LID3, G=(1e-4, 0, 0)),
 ]
 
 

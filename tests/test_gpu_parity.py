@@ -134,6 +134,13 @@ CASES = [
     c3("d3q19-mixed", (12, 9, 11), (2, 2, 1, 3, 0, 0), pw=[2e-3, 0, 0, 0, 0, 0], uw=LID3, mesh=(0, 1, 0),
        k_stretch=1.2, dt=0.3),
     c3("d3q19-minimal", (2, 2, 2), (1, 1, 3, 3, 1, 1), uw=LID3),
+    # degenerate periodic axes: a march axis of one plane (the plane ring
+    # holds the same plane three times), a tile axis of one column (both
+    # halo columns are the cell itself), two cells on two periodic axes
+    c3("d3q19-one-plane-periodic-z", (9, 7, 1), (1, 1, 1, 1, 0, 0), uw=LID3),
+    c3("d3q19-one-column-periodic-x", (1, 6, 5), (0, 0, 3, 3, 1, 1), uw=LID3, G=(1e-4, 0, 0)),
+    c3("d3q19-two-cell-periodic-yz", (5, 2, 2), (1, 1, 0, 0, 0, 0),
+       uw=[[0, 0.01, 0], [0, 0, 0.01]] + [[0, 0, 0]] * 4),
 ]
 
 
