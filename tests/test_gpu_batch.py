@@ -117,6 +117,52 @@ def test_batch_matches_oracle():
         B.close()
 
 
+def d3q19_set(with_forces):
+    """uneven D3Q19 instances, degenerate ones included: a cavity, the
+    2x2x2 minimum, a one-column periodic axis, a one-plane periodic march
+    axis, a stretched duct, a fully periodic box"""
+    lid = [[0, 0, 0], [0, 0, 0], [0, 0, 0], [0.05, 0, 0], [0, 0, 0], [0, 0, 0]]
+
+    def c(n, bc, **kw):
+        d = dict(lattice=19, dtype="f64", n=n, L=tuple(float(v) for v in n), rho0=1.0, RT=1 / 3, tau=0.3,
+                 dt=0.5, bc=bc, uw=lid)
+        d.update(kw)
+        return d
+
+    cfgs = [c((20, 17, 9), (1,) * 6, tau=0.25),
+            c((2, 2, 2), (1, 1, 3, 3, 1, 1)),
+            c((1, 6, 5), (0, 0, 3, 3, 1, 1), G=(1e-4, 0, 0)),
+            c((9, 7, 1), (1, 1, 1, 1, 0, 0), omega=0.2, G=(0, 1e-4, 0)),
+            c((8, 12, 10), (0, 0, 3, 3, 3, 3), mesh=(0, 1, 1), k_stretch=1.3, dt=0.3, G=(2e-4, 0, 0)),
+            c((13, 11, 9), (0,) * 6, G=(1e-4, 0, -2e-4), omega=0.1, phase=0.4)]
+    forces = [None] * len(cfgs)
+    if with_forces:
+        for i in (0, 3, 5):
+            Q, D, shp = M.shape_of(cfgs[i])
+            forces[i] = torch.from_numpy(field(70 + i, (D,) + shp, 1e-4)).to("cuda")
+    return cfgs, forces
+
+
+@pytest.mark.parametrize("with_forces", [False, True], ids=["no-field", "force-fields"])
+def test_batch_d3q19_matches_oracle(with_forces):
+    cfgs, forces = d3q19_set(with_forces)
+    say(f"[batch d3q19 vs oracle] fields={with_forces} sizes={[c['n'] for c in cfgs]}")
+    B = M.BatchSolver(cfgs, forces=forces)
+    try:
+        f0 = [B.state(i).cpu().numpy() for i in range(len(cfgs))]
+        B.run(6)
+        B.run(5)
+        torch.cuda.synchronize()
+        for i, c in enumerate(cfgs):
+            oc = {k: v for k, v in c.items() if k != "dtype"}
+            fr = None if forces[i] is None else forces[i].cpu().numpy()
+            ref = O.run(oc, f0[i], 11, force=fr)
+            got = B.state(i).cpu().numpy()
+            assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12, c["n"]
+    finally:
+        B.close()
+
+
 def test_batch_rejects_mixed_lattices():
     say("[batch invalid]")
     a = instance_cfg(batch_instances(1, 1)[0], "f64", 8)
