@@ -32,7 +32,8 @@ def periodic_cfg(lat, n, mesh=0, **kw):
     return d
 
 
-@pytest.mark.parametrize("lat,n,mesh", [(9, (37, 29), 0), (9, (21, 18), 1), (19, (13, 11, 9), 0)])
+@pytest.mark.parametrize("lat,n,mesh", [(9, (37, 29), 0), (9, (21, 18), 1), (19, (13, 11, 9), 0),
+                                        (9, (1, 7), 0), (19, (5, 4, 1), 0), (19, (2, 1, 3), 1)])
 def test_step_adjoint_matches_oracle(lat, n, mesh):
     say(f"[adjoint step] lattice={lat} n={n} mesh={mesh}")
     cfg = periodic_cfg(lat, n, mesh)
@@ -69,6 +70,9 @@ WALL_CASES = [
     ("q9-minimal", 9, (2, 2), (1, 3, 2, 1, 0, 0), 0, MOVING, (0, 0, 1e-3, 0, 0, 0)),
     ("q19-neq-cube", 19, (13, 11, 9), (1,) * 6, 0, LID, (0,) * 6),
     ("q19-mixed-tanh", 19, (9, 12, 7), (3, 2, 1, 3, 0, 0), 1, MOVING, (0, 2e-3, 0, 0, 0, 0)),
+    ("q19-minimal", 19, (2, 2, 2), (1, 1, 3, 3, 2, 1), 0, MOVING, (0, 0, 0, 0, 1e-3, 0)),
+    ("q19-one-column-periodic-x", 19, (1, 6, 5), (0, 0, 3, 3, 1, 1), 1, MOVING, (0,) * 6),
+    ("q19-one-plane-periodic-z", 19, (7, 6, 1), (1, 3, 1, 1, 0, 0), 0, MOVING, (0,) * 6),
 ]
 
 

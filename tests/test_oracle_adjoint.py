@@ -91,6 +91,35 @@ def test_step_adjoint_dot_product_walls(lat, bc, stretch, uw, pw):
     assert np.vdot(vg, gG) == pytest.approx(np.vdot(jg, w), rel=1e-7)
 
 
+DEGENERATE = [
+    (9, (1, 5, 1), (0, 0, 1, 1, 0, 0)),       # one-column periodic axis, NEQ walls
+    (19, (4, 3, 1), (1, 1, 3, 3, 0, 0)),      # one-plane periodic axis
+    (19, (1, 3, 2), (0, 0, 3, 3, 1, 1)),      # one-column periodic axis, BB and NEQ walls
+]
+
+
+@pytest.mark.parametrize("lat,n,bc", DEGENERATE, ids=["q9-one-column", "q19-one-plane", "q19-one-column"])
+def test_step_adjoint_dot_product_degenerate_axes(lat, n, bc):
+    # periodic axes of one cell: the cell is its own neighbour on both sides,
+    # so every interface of that axis couples a cell with itself
+    d = dict(lattice=lat, n=n, L=tuple(float(v) for v in n), mesh=(0, 0, 0), k_stretch=1.5, rho0=1.0, RT=1 / 3,
+             tau=0.45, dt=0.5, bc=bc, uw=MOVING, pw=[0.0] * 6, G=(1e-3, -5e-4, 2e-4), omega=0.7, phase=0.3)
+    D, Q, shp = O.dims(d)
+    Gf = field(51, (D,) + shp, 2e-3)
+    f = perturb(52, O.init(d, rho=1 + field(53, shp, 0.02), u=field(54, (D,) + shp, 0.05), force=Gf), 1e-2)
+    t = 0.4
+    v = field(55, f.shape, 1.0)
+    w = field(56, f.shape, 1.0)
+    vg = field(57, Gf.shape, 1.0)
+    eps = 1e-5
+    jv = (O.step(d, f + eps * v, Gf, t) - O.step(d, f - eps * v, Gf, t)) / (2 * eps)
+    jg = (O.step(d, f, Gf + eps * 1e-2 * vg, t) - O.step(d, f, Gf - eps * 1e-2 * vg, t)) / (2 * eps * 1e-2)
+    gG = np.zeros_like(Gf)
+    jtw = O.step_adjoint(d, f, w, force=Gf, t=t, grad_force=gG)
+    assert np.vdot(v, jtw) == pytest.approx(np.vdot(jv, w), rel=5e-9)
+    assert np.vdot(vg, gG) == pytest.approx(np.vdot(jg, w), rel=1e-7)
+
+
 def test_step_adjoint_wall_columns_by_brute_force():
     # full Jacobian columns of a tiny walled mesh: e_k^T J^T w for a few unit
     # vectors e_k next to walls and corners, each against a central FD
