@@ -351,7 +351,8 @@ constexpr bool own_regs()
     return LAT::Q == 9 || (LAT::Q == 19 && UNI && !FF);
 }
 
-template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN, bool NOG = false, bool ORIG = false>
+template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN, bool NOG = false, bool ORIG = false,
+          bool LPF = false>
 __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                            T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                            int ck, T* lds)
@@ -443,6 +444,40 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
             }
         }
     };
+    // Late prefetch (FP64 with the own state in registers, single-instance
+    // launches without a force field): the state of plane z+2 is loaded after
+    // the interface stage of plane z, so that its latency overlaps the barrier
+    // wait and the update instead of stalling the next f-bar-plus stage (2 %
+    // at 128^3; the FP32, batched and force-field instances run out of
+    // registers with it: D2Q9 512^2 with a field 30 -> 39 us).
+    constexpr bool LP = LPF && OWN && sizeof(T) == 8;
+    T pn[K], pnr = T(0), pgn[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < K; ++k) pn[k] = T(0);
+    int pn_plane = -0x7fffffff;  // plane held in pn
+    auto prefetch = [&](int p) {
+        if (cell_col) {
+            const long long ci = plane_cell(p);
+            const T* fp = fin + ci + q0off;
+#pragma unroll
+            for (int k = 0; k < K; ++k) pn[k] = fp[k * qstep];
+            pnr = fin[ci + roff];
+            if (force) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) pgn[a] = force[(long long)a * P.nc + ci];
+            }
+        }
+        pn_plane = p;
+    };
+    // load_plane's effect with the prefetched values
+    auto take_plane = [&]() {
+        shift_own();
+#pragma unroll
+        for (int k = 0; k < K; ++k) pf[k] = pn[k];
+        prest = pnr;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) pg[a] = pgn[a];
+    };
     auto compute_plane = [&](int p) {
         if (cell_col) {
             T v[K], vr;
@@ -523,6 +558,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         hi = p0;
     }
     if (PF && hi + 1 <= p1 && computed(hi + 1)) load_plane(hi + 1);
+    if (LP && hi + 1 <= p1 && computed(hi + 1)) prefetch(hi + 1);
     // lower march-axis face of the first plane
     T zlo[NM > 0 ? NM : 1];
     if (upd_col) {
@@ -546,7 +582,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                 shift_own();
                 ghost_plane(z + 1, z, z - 1, P.rhi[M]);
             } else {
-                if (!PF) load_plane(z + 1);
+                if (LP && pn_plane == z + 1) take_plane();
+                else if (!PF) load_plane(z + 1);
                 compute_plane(z + 1);
             }
             hi = z + 1;
@@ -596,6 +633,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
             if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
             else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
         }
+        if (LP && z + 2 <= p1 && computed(z + 2) && pn_plane != z + 2) prefetch(z + 2);
         __syncthreads();
         if (upd_col) {
             const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
@@ -651,7 +689,7 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const Inst<T>& P = *Pp;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    split_body<LAT, T, BX, BY, PF, UNI, own_regs<LAT, T, UNI, FF>(), NOG, ORIG>(P, fin, FF ? force : nullptr, fout, gt, gth,
+    split_body<LAT, T, BX, BY, PF, UNI, own_regs<LAT, T, UNI, FF>(), NOG, ORIG, !FF>(P, fin, FF ? force : nullptr, fout, gt, gth,
                                                                          chunk,
                                                                     tiles0, b % tiles, b / tiles,
                                    reinterpret_cast<T*>(smem_raw));
