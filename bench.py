@@ -260,6 +260,31 @@ def bench_adjoint(n=256, steps=50, warmup=5, walls=False, full_steps=2000):
     return out
 
 
+def device_context(step_gbs):
+    """HIP version torch was built with, the GPU architecture and the
+    bandwidth of a plain 512 MiB
+    device-to-device copy (bytes read + written / time), the practically
+    reachable HBM rate that the step's algorithmic rate compares with"""
+    import torch
+
+    src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return {"torch_hip": torch.version.hip, "arch": torch.cuda.get_device_properties(0).gcnArchName,
+            "copy_512MiB_GBps": round(gbs, 1), "step_vs_copy": round(step_gbs / gbs, 4)}
+
+
 def full_gradient_time(cfg, Gtar, nsteps, ms_forward):
     """Wall time of one whole gradient (checkpointed forward, recompute and
     adjoint steps, initial-state and read-out VJPs, host calls included) of
@@ -559,6 +584,7 @@ def main():
         also["adjoint"] = bench_adjoint()
         also["adjoint_walls"] = bench_adjoint(walls=True)
         res["also"] = also
+        res["context"] = device_context(achieved)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)
