@@ -262,9 +262,9 @@ def bench_adjoint(n=256, steps=50, warmup=5, walls=False, full_steps=2000):
 
 def device_context(step_gbs):
     """HIP version torch was built with, the GPU architecture and the
-    bandwidth of a plain 512 MiB
-    device-to-device copy (bytes read + written / time), the practically
-    reachable HBM rate that the step's algorithmic rate compares with"""
+    bandwidth of a plain 512 MiB device-to-device copy (bytes read + written
+    / time), the practically reachable HBM rate that the step's algorithmic
+    rate compares with"""
     import torch
 
     src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
