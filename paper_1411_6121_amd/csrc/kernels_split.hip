@@ -109,16 +109,18 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
         }
     }
     const T rho = (rh + partner(rh)) + fr;
+    // original model: u = c j / rho (+ h G), with one division per point
+    const T cir = ORIG ? P.c / rho : T(0);
     T G[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)}, us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const T jh = sg * sj[a];
         const T j = jh + partner(jh);
         if constexpr (NOG) {
-            u[a] = ORIG ? P.c * j / rho : P.crho * j;
+            u[a] = ORIG ? cir * j : P.crho * j;
         } else {
             G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
-            u[a] = vel_from<T, ORIG>(P, rho, j, G[a], P.h);
+            u[a] = ORIG ? cir * j + P.h * G[a] : vel_from<T, false>(P, rho, j, G[a], P.h);
         }
         us[a] = sg * u[a];
         Gs[a] = sg * G[a];
@@ -203,12 +205,13 @@ __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT
         }
     }
     rho = (rh + partner(rh)) + fr;
+    const T cir = ORIG ? P.c / rho : T(0);  // original model, as in phi_half
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const T jh = sg * sj[a];
         const T j = jh + partner(jh);
-        if constexpr (NOG) u[a] = ORIG ? P.c * j / rho : P.crho * j;
-        else u[a] = vel_from<T, ORIG>(P, rho, j, G[a], T(0.5) * P.h);
+        if constexpr (NOG) u[a] = ORIG ? cir * j : P.crho * j;
+        else u[a] = ORIG ? cir * j + (T(0.5) * P.h) * G[a] : vel_from<T, false>(P, rho, j, G[a], T(0.5) * P.h);
     }
 #pragma unroll
     for (int a = D; a < 3; ++a) u[a] = T(0);
