@@ -79,9 +79,17 @@ def test_original_model_init_and_moments(lat):
         M.dugks_destroy(ctx)
 
 
-def test_original_model_f32_velocity():
-    cfg = c2("of32", (24, 20), (1, 1, 1, 1, 0, 0), uw=LID, tau=0.2, model=1)
-    say("[original model f32]")
+ORIG_F32 = [
+    c2("of32", (24, 20), (1, 1, 1, 1, 0, 0), uw=LID, tau=0.2, model=1),
+    c3("of32-d3q19", (10, 9, 8), (1,) * 6, uw=LID3, tau=0.2, model=1),
+    c3("of32-d3q19-tanh-bb", (9, 10, 8), (3, 3, 1, 1, 3, 3), uw=LID3, tau=0.2, model=1, mesh=(1, 1, 1),
+       k_stretch=1.5, dt=0.25),
+]
+
+
+@pytest.mark.parametrize("cfg", ORIG_F32, ids=[c["name"] for c in ORIG_F32])
+def test_original_model_f32_velocity(cfg):
+    say(f"[original model f32] {cfg['name']}")
     f0 = O.init(cfg)
     ref = O.run(cfg, f0, 500)
     got = gpu_run(dict(cfg, dtype="f32"), f0, 500)
