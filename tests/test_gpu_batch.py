@@ -117,14 +117,14 @@ def test_batch_matches_oracle():
         B.close()
 
 
-def d3q19_set(with_forces):
+def d3q19_set(with_forces, dtype="f64"):
     """uneven D3Q19 instances, degenerate ones included: a cavity, the
     2x2x2 minimum, a one-column periodic axis, a one-plane periodic march
     axis, a stretched duct, a fully periodic box"""
     lid = [[0, 0, 0], [0, 0, 0], [0, 0, 0], [0.05, 0, 0], [0, 0, 0], [0, 0, 0]]
 
     def c(n, bc, **kw):
-        d = dict(lattice=19, dtype="f64", n=n, L=tuple(float(v) for v in n), rho0=1.0, RT=1 / 3, tau=0.3,
+        d = dict(lattice=19, dtype=dtype, n=n, L=tuple(float(v) for v in n), rho0=1.0, RT=1 / 3, tau=0.3,
                  dt=0.5, bc=bc, uw=lid)
         d.update(kw)
         return d
@@ -139,7 +139,7 @@ def d3q19_set(with_forces):
     if with_forces:
         for i in (0, 3, 5):
             Q, D, shp = M.shape_of(cfgs[i])
-            forces[i] = torch.from_numpy(field(70 + i, (D,) + shp, 1e-4)).to("cuda")
+            forces[i] = torch.from_numpy(field(70 + i, (D,) + shp, 1e-4)).to("cuda", dtype=M.torch_dtype(cfgs[i]))
     return cfgs, forces
 
 
@@ -159,6 +159,29 @@ def test_batch_d3q19_matches_oracle(with_forces):
             ref = O.run(oc, f0[i], 11, force=fr)
             got = B.state(i).cpu().numpy()
             assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12, c["n"]
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("with_forces", [False, True], ids=["no-field", "force-fields"])
+def test_batch_d3q19_f32_velocity(with_forces):
+    # FP32 batch against the FP64 oracle from the same (rounded) initial
+    # states: velocities within 2e-5 of the lid speed after 100 steps
+    cfgs, forces = d3q19_set(with_forces, "f32")
+    say(f"[batch d3q19 f32 vs oracle] fields={with_forces}")
+    B = M.BatchSolver(cfgs, forces=forces)
+    try:
+        f0 = [B.state(i).double().cpu().numpy() for i in range(len(cfgs))]
+        B.run(100)
+        torch.cuda.synchronize()
+        for i, c in enumerate(cfgs):
+            oc = {k: v for k, v in c.items() if k != "dtype"}
+            fr = None if forces[i] is None else forces[i].double().cpu().numpy()
+            ref = O.run(oc, f0[i], 100, force=fr)
+            t = 100 * c["dt"]
+            _, u_ref, _, _ = O.moments(oc, ref, force=fr, t=t)
+            _, u_got, _, _ = O.moments(oc, B.state(i).double().cpu().numpy(), force=fr, t=t)
+            assert np.abs(u_got - u_ref).max() / 0.05 < 2e-5, c["n"]
     finally:
         B.close()
 
