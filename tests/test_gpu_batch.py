@@ -186,6 +186,28 @@ def test_batch_d3q19_f32_velocity(with_forces):
         B.close()
 
 
+@pytest.mark.parametrize("with_forces", [False, True], ids=["no-field", "force-fields"])
+def test_batch_d3q19_graph_replays_equal_eager_runs(with_forces):
+    # graph replays of the D3Q19 batch (the time factor comes from the
+    # device step counter) against eager launches, with eager work between
+    cfgs, forces = d3q19_set(with_forces)
+    say(f"[batch d3q19 graph replay] fields={with_forces}")
+    Bg = M.BatchSolver(cfgs, forces=forces)
+    Be = M.BatchSolver(cfgs, forces=forces)
+    try:
+        for rep in range(3):
+            Bg.run(3, use_graph=True)
+            Be.run(3, use_graph=False)
+            torch.cuda.synchronize()
+            assert torch.isfinite(Be.f.sum())
+            torch.cuda.synchronize()
+            for i in range(len(cfgs)):
+                assert torch.equal(Bg.state(i), Be.state(i)), f"replay {rep} instance {i}"
+    finally:
+        Bg.close()
+        Be.close()
+
+
 def test_batch_rejects_mixed_lattices():
     say("[batch invalid]")
     a = instance_cfg(batch_instances(1, 1)[0], "f64", 8)
