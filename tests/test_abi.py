@@ -68,6 +68,29 @@ def test_invalid_configurations_are_rejected(bad):
     assert ei.value.code == M.EINVAL
 
 
+@pytest.mark.parametrize("bad,why", [
+    (dict(mesh=(5, 0, 0)), "unknown mesh kind"),
+    (dict(n=(1 << 25, 8, 1)), "cell count out of range"),
+    (dict(G=(float("inf"), 0.0, 0.0)), "non-finite acceleration"),
+    (dict(omega=float("nan")), "non-finite omega/phase"),
+    (dict(phase=float("inf")), "non-finite omega/phase"),
+    (dict(bc=(2, 2, 0, 0, 0, 0), pw=[float("nan")] + [0.0] * 5), "non-finite wall pressure"),
+    (dict(bc=(1, 1, 0, 0, 0, 0), uw=[[float("nan"), 0, 0]] + [[0, 0, 0]] * 5), "non-finite wall velocity"),
+    (dict(bc=(2, 2, 0, 0, 0, 0), pw=[-1.0, 0, 0, 0, 0, 0]), "non-positive density"),  # rho0 + p/RT <= 0
+    (dict(lattice=19, n=(1 << 14, 1 << 14, 1 << 14), L=(1.0, 1.0, 1.0)), "problem too large"),  # > 2^40 values
+    (dict(rho0=0.0), "must be positive and finite"),
+    (dict(tau=float("inf")), "must be positive and finite"),
+])
+def test_invalid_configurations_name_the_reason(bad, why):
+    # validation precedes any device work, so init reports it without a GPU
+    lib = M.load()
+    h = ctypes.c_void_p(123)
+    rc = lib.dugks_init(ctypes.byref(M.config(base_cfg(**bad))), None, None, None, ctypes.c_void_p(1), None,
+                        ctypes.byref(h))
+    assert rc == M.EINVAL and h.value is None
+    assert why.encode() in lib.dugks_last_error(None)
+
+
 def test_invalid_init_reports_einval_without_device():
     lib = M.load()
     h = ctypes.c_void_p(123)
