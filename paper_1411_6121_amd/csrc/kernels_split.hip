@@ -283,13 +283,41 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
     }
 }
 
+// The force field of the three ring planes in LDS (D2Q9 launches with a
+// field), laid out [plane slot][component][column]: at(d, A, off) is
+// component d at offset off along axis A from the thread's column in the
+// current plane.  g == nullptr: the field is read from global memory.
+template <typename T, int BX, int BY>
+struct RingForce {
+    const T* g;
+    int cur, dz_up, dz_dn;
+    static constexpr int SQ = BX * BY;
+    __device__ __forceinline__ T at(int d, int A, int off) const
+    {
+        return g[cur + d * SQ + (A == 0 ? off : (off > 0 ? dz_up : (off < 0 ? dz_dn : 0)))];
+    }
+};
+
+// acceleration on the interface of axis A between the cells at offsets off
+// and off+1 (weight w of the right one), from the LDS ring; the same
+// expression as face_force
+template <class LAT, typename T, class GV>
+__device__ __forceinline__ void face_force_ring(const Inst<T>& P, const GV& gv, int A, int off, T w, T gth, T* G)
+{
+#pragma unroll
+    for (int d = 0; d < LAT::D; ++d) {
+        const T gl = gv.at(d, A, off), gr = gv.at(d, A, off + 1);
+        G[d] = gth * (P.G0[d] + (gl + w * (gr - gl)));
+    }
+}
+
 // The interface of axis A with index f between the cells at offsets off and
 // off+1: steps 3-7 for the lane's velocities; out[half_cross_slot] receives
 // f (step 7) of the lane's velocities crossing the face.
-template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false>
-__device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
-                                          int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
-                                          const CellMetric<T>& mz, T sg, int sgi, T* out)
+template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false, class GV>
+__device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const GV& gv,
+                                          const int* ci, int off, int f, T gth, const CellMetric<T>& mx,
+                                          const CellMetric<T>& my, const CellMetric<T>& mz, T sg, int sgi, T* out)
 {
     constexpr int K = LAT::REST;
     const AxisMetric<T>& m = P.m[A];
@@ -304,13 +332,17 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
         const int oo = wall_lo ? off + 1 : off - 1;
         const T wo = UNI ? T(0.5) : m.w[fo];
         recon_half<LAT, T, ACC, A, UNI>(P, ph, oo, wo, UNI ? P.ugn[A] : m.gn[fo], mx, my, mz, sg, fb, fr);
-        if constexpr (!NOG) face_force<LAT, T>(P, force, A, fo, wo, ci, gth, G);
+        if constexpr (!NOG) {
+            if (LAT::D == 2 && gv.g) face_force_ring<LAT, T>(P, gv, A, oo, wo, gth, G);
+            else face_force<LAT, T>(P, force, A, fo, wo, ci, gth, G);
+        }
         neq_capture_half<LAT, T, A, NOG, ORIG>(P, fb, fr, G, sg, info);
         asm volatile("" ::: "memory");
     }
     const T w = UNI ? T(0.5) : m.w[f];
     recon_half<LAT, T, ACC, A, UNI>(P, ph, off, w, UNI ? P.ugn[A] : m.gn[f], mx, my, mz, sg, fb, fr);
     if constexpr (NOG) G[0] = G[1] = G[2] = T(0);
+    else if (LAT::D == 2 && gv.g) face_force_ring<LAT, T>(P, gv, A, off, w, gth, G);
     else face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
     if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi);
     if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi);
@@ -366,6 +398,9 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     constexpr int SQ = BX * BY;
     T* fxb = lds + 3 * Q * SQ;   // [2][NX][BY][BX] upper x faces, per half
     T* fyb = fxb + 2 * NX * SQ;  // [2][NY][BY][BX] upper y faces (3-D)
+    // D2Q9: the force field of the ring planes, [3][D][BY][BX], after the
+    // x faces (no y-face buffer in 2-D)
+    T* gring = fxb + 2 * NX * SQ;
     const int tid = threadIdx.x;
     const int h = (tid >> 5) & 1;
     const int col = (tid >> 6) * 32 + (tid & 31);
@@ -401,6 +436,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                        g[1] <= P.n[1] - 1;
 
     const bool any_ghost = __syncthreads_or(ghost_col) != 0;
+    const bool gr_on = (D == 2) && force != nullptr;
+    auto gslot = [&](int p, int d) { return (ring(p) * D + d) * SQ + ty * BX + tx; };
     const int nM = P.n[M];
     const int p0 = ck * chunk;
     const int p1 = min(p0 + chunk, nM);
@@ -488,6 +525,10 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
 #pragma unroll
             for (int k = 0; k < K; ++k) lds[lds_el(p, hs + k, 0, 0)] = v[k];
             if (h == 0) lds[lds_el(p, K, 0, 0)] = vr;
+            if (gr_on && h == 0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) gring[gslot(p, d)] = pg[d];
+            }
         }
         __syncthreads();
         if (!any_ghost) return;
@@ -523,6 +564,18 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
 #pragma unroll
             for (int k = 0; k < K; ++k) lds[lds_el(p, hs + k, 0, 0)] = acc[k];
             if (h == 0) lds[lds_el(p, K, 0, 0)] = acc[K];
+            if (gr_on && h == 0) {
+                // the force field's ghost rule is that of f-bar-plus
+                T ga[3] = {T(0), T(0), T(0)};
+                for (int i1 = 0; i1 < cnt[1]; ++i1)
+                    for (int i0 = 0; i0 < cnt[0]; ++i0) {
+                        const T w = wt[0][i0] * wt[1][i1];
+#pragma unroll
+                        for (int d = 0; d < D; ++d) ga[d] += w * gring[gslot(p, d) + off[1][i1] * BX + off[0][i0]];
+                    }
+#pragma unroll
+                for (int d = 0; d < D; ++d) gring[gslot(p, d)] = ga[d];
+            }
         }
         __syncthreads();
     };
@@ -535,6 +588,11 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                     (T(1) - r) * lds[lds_el(a, hs + k, 0, 0)] + r * lds[lds_el(b, hs + k, 0, 0)];
             if (h == 0)
                 lds[lds_el(p, K, 0, 0)] = (T(1) - r) * lds[lds_el(a, K, 0, 0)] + r * lds[lds_el(b, K, 0, 0)];
+            if (gr_on && h == 0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    gring[gslot(p, d)] = (T(1) - r) * gring[gslot(a, d)] + r * gring[gslot(b, d)];
+            }
         }
         __syncthreads();
     };
@@ -542,6 +600,10 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         const int slot = Q * SQ;
         return HalfPhi<LAT, T, BX, BY>{lds, ring(z) * slot + ty * BX + tx, hs * SQ, (ring(z + 1) - ring(z)) * slot,
                                        (ring(z - 1) - ring(z)) * slot};
+    };
+    auto gview = [&](int z) {
+        return RingForce<T, BX, BY>{gr_on ? gring : nullptr, ring(z) * D * SQ + ty * BX + tx,
+                                    (ring(z + 1) - ring(z)) * D * SQ, (ring(z - 1) - ring(z)) * D * SQ};
     };
     auto computed = [&](int p) { return perM || p < nM; };
 
@@ -571,8 +633,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         ci[2] = (D == 3) ? p0 : 0;
         const CellMetric<T> cmm = load_metric(P, M, p0);
         const auto ph = phi_view(p0);
-        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
-        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
+        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(p0), ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
+        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(p0), ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
     }
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
@@ -619,22 +681,22 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         T zhi[NM > 0 ? NM : 1];
         if (xface) {
             T v[NX];
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
 #pragma unroll
             for (int kc = 0; kc < NX; ++kc) fxb[((h * NX + kc) * BY + ty) * BX + tx] = v[kc];
         }
         if constexpr (D == 3) {
             if (yface) {
                 T v[NY];
-                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI, NOG, ORIG>(P, ph, force, ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
 #pragma unroll
                 for (int kc = 0; kc < NY; ++kc) fyb[((h * NY + kc) * BY + ty) * BX + tx] = v[kc];
             }
         }
         if (upd_col) {
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
         }
         if (LP && z + 2 <= p1 && computed(z + 2) && pn_plane != z + 2) prefetch(z + 2);
         __syncthreads();
@@ -738,7 +800,8 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
 template <class LAT, typename T, int BX, int BY>
 static size_t split_lds()
 {
-    return (size_t)(3 * LAT::Q + 2 * half_cross_count<LAT, 0>() + (LAT::D == 3 ? 2 * half_cross_count<LAT, 1>() : 0)) *
+    return (size_t)(3 * LAT::Q + 2 * half_cross_count<LAT, 0>() + (LAT::D == 3 ? 2 * half_cross_count<LAT, 1>() : 0) +
+                    (LAT::D == 2 ? 3 * LAT::D : 0)) *
            BX * BY * sizeof(T);
 }
 
