@@ -49,17 +49,19 @@ class _Rollout(torch.autograd.Function):
         lam2 = torch.empty_like(lam)
         dugks_moments_vjp(h, lam, None, grad_u, nsteps * dt, gforce)
         starts = sorted(ckpt.keys())
+        # one segment's states, recomputed step by step straight into their
+        # slots (slot 0 is the checkpoint itself)
+        seg_states = torch.empty((seg - 1, Q) + shp, dtype=force.dtype, device=force.device) if seg > 1 else None
         for s0 in reversed(starts):
             s1 = min(s0 + seg, nsteps)
-            states = [ckpt[s0]]
-            cur = ckpt[s0].clone()
-            nxt = torch.empty_like(cur)
+
+            def state(n):
+                return ckpt[s0] if n == s0 else seg_states[n - s0 - 1]
+
             for n in range(s0, s1 - 1):
-                dugks_step(h, cur, nxt, force, n * dt)
-                cur, nxt = nxt, cur
-                states.append(cur.clone())
+                dugks_step(h, state(n), state(n + 1), force, n * dt)
             for n in reversed(range(s0, s1)):
-                dugks_step_adjoint(h, states[n - s0], lam, lam2, force, n * dt, gforce)
+                dugks_step_adjoint(h, state(n), lam, lam2, force, n * dt, gforce)
                 lam, lam2 = lam2, lam
         gu0 = torch.zeros_like(u0)
         dugks_init_vjp(h, lam, u0, force, 0.0, gu0, gforce)
