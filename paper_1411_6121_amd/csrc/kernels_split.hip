@@ -396,6 +396,15 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     constexpr int NX = half_cross_count<LAT, 0>(), NY = half_cross_count<LAT, 1>();
     constexpr int NM = half_cross_count<LAT, M>();
     constexpr int SQ = BX * BY;
+    // PHIU (FP32 D3Q19 without acceleration, single-instance launches): the
+    // update needs no own state, since rho and j of f-bar-plus equal those
+    // of f-tilde without acceleration: feq follows from the ring and
+    // f-tilde(n+1) = phi + B1 / (3 (1 - B1)) (feq - phi) - fluxes.  The
+    // registers of the own-state ring then hold the late prefetch instead
+    // (4 waves per SIMD leave 128 registers).
+    constexpr bool PHIU = NOG && !ORIG && LAT::Q == 19 && sizeof(T) == 4 && LPF;
+    constexpr bool OWNR = OWN && !PHIU;
+    const T Bu = P.B1 / (T(3) * (T(1) - P.B1));
     T* fxb = lds + 3 * Q * SQ;   // [2][NX][BY][BX] upper x faces, per half
     T* fyb = fxb + 2 * NX * SQ;  // [2][NY][BY][BX] upper y faces (3-D)
     // D2Q9: the force field of the ring planes, [3][D][BY][BX], after the
@@ -453,14 +462,14 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // element of (plane p, slot s, this column + (dx, dy))
     auto lds_el = [&](int p, int s, int dx, int dy) -> int { return ((ring(p) * Q + s) * BY + ty + dy) * BX + tx + dx; };
 
-    static_assert(!(PF && OWN), "the own-state registers assume no plane prefetch");
+    static_assert(!(PF && OWNR), "the own-state registers assume no plane prefetch");
     T pf[K], prest = T(0), pg[3] = {T(0), T(0), T(0)};
     // OWN: f-tilde of plane hi - 1 (the plane before the last one loaded)
     T fo[K], fore = T(0);
 #pragma unroll
     for (int k = 0; k < K; ++k) pf[k] = fo[k] = T(0);
     auto shift_own = [&]() {
-        if constexpr (OWN) {
+        if constexpr (OWNR) {
 #pragma unroll
             for (int k = 0; k < K; ++k) fo[k] = pf[k];
             fore = prest;
@@ -488,9 +497,10 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // launches without a force field): the state of plane z+2 is loaded after
     // the interface stage of plane z, so that its latency overlaps the barrier
     // wait and the update instead of stalling the next f-bar-plus stage (2 %
-    // at 128^3; the FP32, batched and force-field instances run out of
-    // registers with it: D2Q9 512^2 with a field 30 -> 39 us).
-    constexpr bool LP = LPF && OWN && sizeof(T) == 8;
+    // at 128^3; the batched and force-field instances, and FP32 with the
+    // own-state ring, run out of registers with it: D2Q9 512^2 with a field
+    // 30 -> 39 us; FP32 takes it with PHIU).
+    constexpr bool LP = LPF && ((OWNR && sizeof(T) == 8) || PHIU);
     T pn[K], pnr = T(0), pgn[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < K; ++k) pn[k] = T(0);
@@ -665,7 +675,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         // the cell's own state for Eq. (f_tilde_+)
         T fz[K], fzr = T(0);
         auto load_own = [&]() {
-            if constexpr (OWN) {  // plane z = hi - 1
+            if constexpr (OWNR) {  // plane z = hi - 1
 #pragma unroll
                 for (int k = 0; k < K; ++k) fz[k] = fo[k];
                 fzr = fore;
@@ -702,15 +712,42 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         __syncthreads();
         if (upd_col) {
             const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+            T acc[K], accr;
+            if constexpr (PHIU) {
+                T pv[K];
+                T rh = T(0), sj[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    pv[k] = ph.get(k, ph.cur);
+                    rh += pv[k];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        if (LAT::e(k, a) == 1) sj[a] += pv[k];
+                        if (LAT::e(k, a) == -1) sj[a] -= pv[k];
+                    }
+                }
+                const T pr = ph.rest(ph.cur);
+                const T rho = (rh + partner(rh)) + pr;
+                T us[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const T jh = sg * sj[a];
+                    us[a] = sg * (P.crho * (jh + partner(jh)));
+                }
+                const EqPt<T> E = eq_point<LAT, T, false>(P, rho, us, nullptr);
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc[k] = pv[k] + Bu * (feq_pt<LAT, T, false>(P, E, k) - pv[k]);
+                accr = pr + Bu * (feq_pt<LAT, T, false>(P, E, LAT::REST) - pr);
+            } else {
             if (!PF) load_own();
-            T acc[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const T p = ph.get(k, ph.cur);
                 acc[k] = p + (p - fz[k]) * T(1.0 / 3.0);  // Eq. (f_tilde_+)
             }
             const T pr = ph.rest(ph.cur);
-            const T accr = pr + (pr - fzr) * T(1.0 / 3.0);
+            accr = pr + (pr - fzr) * T(1.0 / 3.0);
+            }
             const T sx = sg * ((UNI ? P.ufdx[0] : cmx.fdx) * P.c), sm = sg * ((UNI ? P.ufdx[M] : cmm.fdx) * P.c);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
