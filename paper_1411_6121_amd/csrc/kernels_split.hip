@@ -396,13 +396,15 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     constexpr int NX = half_cross_count<LAT, 0>(), NY = half_cross_count<LAT, 1>();
     constexpr int NM = half_cross_count<LAT, M>();
     constexpr int SQ = BX * BY;
-    // PHIU (FP32 D3Q19 without acceleration, single-instance launches): the
-    // update needs no own state, since rho and j of f-bar-plus equal those
-    // of f-tilde without acceleration: feq follows from the ring and
-    // f-tilde(n+1) = phi + B1 / (3 (1 - B1)) (feq - phi) - fluxes.  The
-    // registers of the own-state ring then hold the late prefetch instead
-    // (4 waves per SIMD leave 128 registers).
-    constexpr bool PHIU = NOG && !ORIG && LAT::Q == 19 && sizeof(T) == 4 && LPF;
+    // PHIU (single-instance launches without acceleration: FP32 D3Q19, and
+    // D3Q27): the update needs no own state, since rho and j of f-bar-plus
+    // equal those of f-tilde without acceleration: feq follows from the ring
+    // and f-tilde(n+1) = phi + B1 / (3 (1 - B1)) (feq - phi) - fluxes.  FP32
+    // D3Q19 (4 waves per SIMD, 128 registers) spends the freed own-state
+    // registers on the late prefetch; D3Q27, which keeps no own state in
+    // registers, saves the second read of it (FP32 also takes the prefetch,
+    // FP64 has no registers for it).
+    constexpr bool PHIU = NOG && !ORIG && LPF && ((LAT::Q == 19 && sizeof(T) == 4) || LAT::Q == 27);
     constexpr bool OWNR = OWN && !PHIU;
     const T Bu = P.B1 / (T(3) * (T(1) - P.B1));
     T* fxb = lds + 3 * Q * SQ;   // [2][NX][BY][BX] upper x faces, per half
@@ -499,8 +501,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // wait and the update instead of stalling the next f-bar-plus stage (2 %
     // at 128^3; the batched and force-field instances, and FP32 with the
     // own-state ring, run out of registers with it: D2Q9 512^2 with a field
-    // 30 -> 39 us; FP32 takes it with PHIU).
-    constexpr bool LP = LPF && ((OWNR && sizeof(T) == 8) || PHIU);
+    // 30 -> 39 us; FP32 takes it with PHIU, D3Q27 FP64 does not).
+    constexpr bool LP = LPF && ((OWNR && sizeof(T) == 8) || (PHIU && (LAT::Q == 19 || sizeof(T) == 4)));
     T pn[K], pnr = T(0), pgn[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < K; ++k) pn[k] = T(0);
