@@ -882,8 +882,13 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     // source term of Eq. (S) (bitwise the same results, fewer operations)
     const bool nog = !force && P.G0[0] == T(0) && P.G0[1] == T(0) && P.G0[2] == T(0);
     if (P.orig) {
-        // the original-model equilibrium (launches without a force field)
-        if (P.uni) return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+        // the original-model equilibrium (launches without a force field;
+        // without acceleration the source-free instances, bitwise the same)
+        if (P.uni) {
+            if (nog) return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true, true, true>(ctx, P, fin, fout, force, t, st, chunk);
+            return launch_split_ff<LAT, T, BX, BY, MINW_UF, PF, false, true, false, true>(ctx, P, fin, fout, force, t, st, chunk);
+        }
+        if (nog) return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, false, true, true>(ctx, P, fin, fout, force, t, st, chunk);
         return launch_split_ff<LAT, T, BX, BY, MINW, PF, false, false, false, true>(ctx, P, fin, fout, force, t, st, chunk);
     }
     if (P.uni) {
