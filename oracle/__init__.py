@@ -76,6 +76,8 @@ def _load():
         lib.oracle_force_term.argtypes = [C, ctypes.c_double, P, P, P]
         lib.oracle_init.argtypes = [C, P, P, P, ctypes.c_double, P]
         lib.oracle_step.argtypes = [C, P, P, P, ctypes.c_double]
+        lib.oracle_run.argtypes = [C, P, P, P, ctypes.c_double, ctypes.c_int]
+        lib.oracle_interface_values.argtypes = [C, ctypes.c_int, P, P]
         lib.oracle_moments.argtypes = [C, P, P, ctypes.c_double, P, P, P, P]
         lib.oracle_step_adjoint.argtypes = [C, P, P, ctypes.c_double, P, P, P]
         lib.oracle_init_adjoint.argtypes = [C, P, P, ctypes.c_double, P, P, P]
@@ -195,12 +197,28 @@ def step(d: dict, f, force=None, t: float = 0.0):
 
 
 def run(d: dict, f, nsteps: int, force=None, t0: float = 0.0):
+    """nsteps steps from t0; step i starts at t0 + i dt"""
+    lib = _load()
     f = _arr(f)
-    t = t0
-    for _ in range(nsteps):
-        f = step(d, f, force, t)
-        t += float(d["dt"])
-    return f
+    force = _arr(force)
+    out = np.empty_like(f)
+    _check(lib.oracle_run(ctypes.byref(_cfg(d)), _p(f), _p(out), _p(force), t0, int(nsteps)), "run")
+    return out
+
+
+def interface_values(d: dict, axis: int, phi):
+    """f-bar on every interface of `axis` (Eq. (gradient), before wall rules)
+    from f-bar-plus values phi[q, z, y, x] at the centres; returns
+    [q, z, y, x] with n+1 entries along `axis`"""
+    lib = _load()
+    D, Q, shp = dims(d)
+    phi = _arr(phi)
+    assert phi.shape == (Q,) + shp
+    fshp = list(shp)
+    fshp[2 - axis] += 1
+    out = np.zeros((Q,) + tuple(fshp))
+    _check(lib.oracle_interface_values(ctypes.byref(_cfg(d)), int(axis), _p(phi), _p(out)), "interface_values")
+    return out
 
 
 def moments(d: dict, f, force=None, t: float = 0.0):

@@ -9,7 +9,7 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(_HERE, "dugks_oracle.c")
     out = os.path.join(_HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
+    cmd = ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
            "-std=c11", "-Wall", "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -3,10 +3,11 @@
  * with body force (arXiv:1411.6121).
  *
  * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
- * benchmark's CPU-baseline leg.  It is deliberately slow and literal:
- * every stage of the Appendix algorithm writes its own array over its own
- * point set (X_c, X_cg, X_b, X_bc), in the order the Appendix gives, with no
- * blocking or fusion.  It shares no code with the HIP path.
+ * benchmark's CPU-baseline leg.  It is deliberately plain: scalar loops over
+ * cell centres and interfaces, FP64, every quantity of an interface
+ * (cross-point values, gradient, wall rule, moments, original distribution,
+ * flux) recomputed where it is used, no blocking or fusion across points.
+ * It shares no code with the HIP path.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (see build.py).
  * Every loop over points writes disjoint outputs in a fixed per-point
@@ -207,8 +208,8 @@ static double feq_q(const octx* o, const oracle_cfg* cfg, int q, double rho, con
  * rho u = sum xi f + rho G dt/2 (model 1) */
 static double mom_density(const oracle_cfg* cfg, double rho) { return cfg->model == 1 ? rho : cfg->rho0; }
 
-/* Eq. (S), evaluated with the incompressible equilibrium as the Appendix
- * does: S = G.(xi - u)/RT feq */
+/* Eq. (S), evaluated with the discrete equilibrium of the model in use (the
+ * incompressible one, Eq. (icfeq), for model 0): S = G.(xi - u)/RT feq */
 static double src_q(const octx* o, const oracle_cfg* cfg, int q, double rho, const double* u,
                     const double* G)
 {
@@ -262,7 +263,8 @@ static inline int pair_id(int a, int b) /* 0:{0,1} 1:{0,2} 2:{1,2} */
     return (a == 0) ? (b == 1 ? 0 : 1) : 2;
 }
 
-/* Step 2 (ghost points X_cg), for any field with ncomp values per point.
+/* Ghost layer of the extended cell set, for any field with ncomp values per
+ * point.
  * Wall axes: linear extrapolation through the two nearest centres to the
  * mirrored ghost centre; periodic axes: copy of the wrapped cell.  Axes are
  * treated one after another over the growing extended range, so edge and
@@ -330,7 +332,7 @@ static void accel_cell(const octx* o, const oracle_cfg* cfg, const double* Gext,
 }
 
 /* acceleration at the face point of axis a with coords c, time factor gt:
- * the spatial part is interpolated like f-bar-plus (step 3) */
+ * the spatial part is interpolated between the two centres like f-bar-plus */
 static void accel_face(const octx* o, const oracle_cfg* cfg, const double* Gext, int a,
                        const int* c, double gt, double* G)
 {
@@ -429,268 +431,367 @@ int oracle_init(const oracle_cfg* cfg, const double* rho, const double* u, const
 }
 
 /* ------------------------------------------------------------------------ */
-/* the step (Appendix, steps 1-9; step 10 is oracle_moments)                 */
+/* one time step t_n -> t_n + dt                                             */
+/*                                                                           */
+/* Written from the equations of Sec. II, organised around its three kinds  */
+/* of work: a transform of every cell centre (Eqs. (macro_values),          */
+/* (f_bar_+)) with the ghost layer of wall axes, a flux routine evaluated    */
+/* once per interface (Eqs. (gradient), (BB)/(NEQ), (original_f),           */
+/* (microflux)), and a conservative update of every cell                     */
+/* (Eqs. (f_tilde_+), (evolution_equation)).                                 */
 /* ------------------------------------------------------------------------ */
-int oracle_step(const oracle_cfg* cfg, const double* fin, double* fout, const double* force,
-                double t)
+
+/* Density and velocity of one point from a distribution set, Eq.
+ * (macro_values): rho = sum f, rho0 u = sum xi f + rho0 G dth (model 0), or
+ * rho u = sum xi f + rho G dth (model 1).  dth is half the interval the
+ * distribution is shifted by: dt/2 for f~ at centres, h/2 for f-bar at
+ * interfaces. */
+static void point_macro(const octx* o, const oracle_cfg* cfg, const double* f, const double* G, double dth,
+                        double* rho, double* u)
 {
-    octx o;
-    if (setup(&o, cfg)) return -1;
-    const int D = o.D, Q = o.Q;
-    const long nc = ncells(&o), nce = ncells_ext(&o);
-    const double dt = cfg->dt, h = 0.5 * dt, tau = cfg->tau, rho0 = cfg->rho0, RT = cfg->RT;
-    /* Eq. (f_bar_+) */
-    const double A1 = (2.0 * tau - h) / (2.0 * tau + dt);
-    const double B1 = 3.0 * h / (2.0 * tau + dt);
-    const double C1 = 3.0 * tau * h / (2.0 * tau + dt);
-    /* step 7, inverse of Eq. (original_f) */
-    const double A7 = 2.0 * tau / (2.0 * tau + h);
-    const double B7 = h / (2.0 * tau + h);
-    const double C7 = tau * h / (2.0 * tau + h);
+    double r = 0.0, m[3] = {0, 0, 0};
+    for (int q = 0; q < o->Q; ++q) {
+        r += f[q];
+        for (int a = 0; a < o->D; ++a) m[a] += o->xi[q][a] * f[q];
+    }
+    const double rm = mom_density(cfg, r);
+    for (int a = 0; a < 3; ++a) u[a] = 0.0;
+    for (int a = 0; a < o->D; ++a) u[a] = (m[a] + rm * G[a] * dth) / rm;
+    *rho = r;
+}
+
+/* equilibrium (Eq. (icfeq), or Eq. (feq) for model 1) and force term
+ * (Eq. (S)) of every velocity at one point */
+static void point_eq(const octx* o, const oracle_cfg* cfg, double rho, const double* u, const double* G,
+                     double* feq, double* S)
+{
+    for (int q = 0; q < o->Q; ++q) {
+        feq[q] = feq_q(o, cfg, q, rho, u);
+        double gx = 0.0;
+        for (int a = 0; a < o->D; ++a) gx += G[a] * (o->xi[q][a] - u[a]);
+        S[q] = gx / cfg->RT * feq[q];
+    }
+}
+
+/* Eq. (f_bar_+) at every cell centre, from f~ at t_n with rho, u of
+ * Eq. (macro_values) and G(x_c, t_n); then the ghost layer (extrapolated on
+ * wall axes, wrapped on periodic ones).  phi is the extended cell array
+ * [cell_ext][q]. */
+static void transform_cells(const octx* o, const oracle_cfg* cfg, const double* fin, const double* Gext,
+                            double gt, double* phi)
+{
+    const int Q = o->Q;
+    const long nc = ncells(o);
+    const double dt = cfg->dt, h = 0.5 * dt, tau = cfg->tau;
+    const double a_f = (2.0 * tau - h) / (2.0 * tau + dt);
+    const double a_eq = 3.0 * h / (2.0 * tau + dt);
+    const double a_s = 3.0 * tau * h / (2.0 * tau + dt);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < o->n[2]; ++k)
+        for (int j = 0; j < o->n[1]; ++j)
+            for (int i = 0; i < o->n[0]; ++i) {
+                const long ci = cell_int(o, i, j, k), ce = cell_ext(o, i, j, k);
+                double f[MAXQ], fe[MAXQ], S[MAXQ], G[3], rho, u[3];
+                for (int q = 0; q < Q; ++q) f[q] = fin[q * nc + ci];
+                accel_cell(o, cfg, Gext, ce, gt, G);
+                point_macro(o, cfg, f, G, dt / 2.0, &rho, u);
+                point_eq(o, cfg, rho, u, G, fe, S);
+                for (int q = 0; q < Q; ++q) phi[ce * Q + q] = a_f * f[q] + a_eq * fe[q] + a_s * S[q];
+            }
+    ghost_fill(o, phi, Q);
+}
+
+/* The cross point of the interface of axis a with index c[a] and the
+ * interface of axis b with index c[b] (c's other entry is a cell index):
+ * its value is the bilinear interpolation of the 2 x 2 block of cells around
+ * it, linear along a on the two rows (weight wa of the upper cell), then
+ * linear along b (weight wb of the upper row).  cell[] receives the block in
+ * the order (lower a, lower b), (upper a, lower b), (lower a, upper b),
+ * (upper a, upper b). */
+typedef struct {
+    long cell[4];
+    double wa, wb;
+} ocross;
+
+static void cross_point_at(const octx* o, int a, int b, const int* c, ocross* x)
+{
+    x->wa = o->w[a][c[a]];
+    x->wb = o->w[b][c[b]];
+    for (int m = 0; m < 4; ++m) {
+        int cc[3] = {c[0], c[1], c[2]};
+        if (!(m & 1)) cc[a] -= 1;
+        if (!(m & 2)) cc[b] -= 1;
+        x->cell[m] = cell_ext(o, cc[0], cc[1], cc[2]);
+    }
+}
+
+static double cross_value(const octx* o, const double* phi, const ocross* x, int q)
+{
+    const int Q = o->Q;
+    const double row_lo = (1.0 - x->wa) * phi[x->cell[0] * Q + q] + x->wa * phi[x->cell[1] * Q + q];
+    const double row_hi = (1.0 - x->wa) * phi[x->cell[2] * Q + q] + x->wa * phi[x->cell[3] * Q + q];
+    return (1.0 - x->wb) * row_lo + x->wb * row_hi;
+}
+
+/* Eqs. (interfaceEvof) and (gradient): f-bar(x_b, t_n + h) =
+ * f-bar-plus(x_b) - h xi . sigma_b at the mid-point of the interface of axis
+ * a with index c[a] (between cells c[a]-1 and c[a]).  f-bar-plus(x_b) is
+ * linear interpolation between the two centres; the normal component of
+ * sigma_b is their difference over their distance, a tangential component b
+ * the difference of the cross-point values at the interface's two edges
+ * along b over the interface width. */
+static void interface_fbar(const octx* o, const double* phi, int a, const int* c, double h, double* fb)
+{
+    const int D = o->D, Q = o->Q;
+    int cl[3] = {c[0], c[1], c[2]};
+    cl[a] -= 1;
+    const long L = cell_ext(o, cl[0], cl[1], cl[2]), R = cell_ext(o, c[0], c[1], c[2]);
+    const double w = o->w[a][c[a]], gn = o->g[a][c[a]];
+    ocross edge_lo[3], edge_hi[3];
+    double inv_width[3] = {0, 0, 0};
+    for (int b = 0; b < D; ++b) {
+        if (b == a) continue;
+        int c_up[3] = {c[0], c[1], c[2]};
+        c_up[b] += 1;
+        cross_point_at(o, a, b, c, &edge_lo[b]);
+        cross_point_at(o, a, b, c_up, &edge_hi[b]);
+        inv_width[b] = 1.0 / o->dl[b][c[b]];
+    }
+    for (int q = 0; q < Q; ++q) {
+        double sig[3] = {0, 0, 0};
+        sig[a] = gn * (phi[R * Q + q] - phi[L * Q + q]);
+        for (int b = 0; b < D; ++b) {
+            if (b == a) continue;
+            sig[b] = (cross_value(o, phi, &edge_hi[b], q) - cross_value(o, phi, &edge_lo[b], q)) * inv_width[b];
+        }
+        double xs = 0.0;
+        for (int b = 0; b < D; ++b) xs += o->xi[q][b] * sig[b];
+        fb[q] = ((1.0 - w) * phi[L * Q + q] + w * phi[R * Q + q]) - h * xs;
+    }
+}
+
+/* Wall interface of side s: the velocities entering the domain (xi.n < 0,
+ * n the outward normal) are replaced by bounce-back, Eq. (BB) with
+ * rho_w = rho0, or by non-equilibrium extrapolation, Eq. (NEQ), whose
+ * non-equilibrium part is taken at x_c, the opposite interface of the same
+ * wall cell (fo: f-bar there, rc/uc its moments).  Velocity condition:
+ * (rho_alpha, u_alpha) = (rc, u_w); pressure condition: (rho0 + p_w/RT, uc).
+ * The rules act on f-bar before its moments are taken. */
+static void wall_condition(const octx* o, const oracle_cfg* cfg, int s, double* fw, const double* fo, double rc,
+                           const double* uc)
+{
+    const int D = o->D, Q = o->Q, a = s / 2;
+    const int out = (s % 2) ? 1 : -1; /* outward normal along a */
+    const double rho0 = cfg->rho0, RT = cfg->RT;
+    if (cfg->bc[s] == OR_BOUNCE_BACK) {
+        double before[MAXQ];
+        for (int q = 0; q < Q; ++q) before[q] = fw[q];
+        for (int q = 0; q < Q; ++q) {
+            if (o->e[q][a] * out >= 0) continue;
+            double xu = 0.0;
+            for (int b = 0; b < D; ++b) xu += o->xi[q][b] * cfg->uw[s][b];
+            fw[q] = before[o->opp[q]] + 2.0 * rho0 * o->W[q] * xu / RT;
+        }
+        return;
+    }
+    double ra, ua[3] = {0, 0, 0};
+    if (cfg->bc[s] == OR_NEQ_VELOCITY) {
+        ra = rc;
+        for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
+    } else {
+        ra = rho0 + cfg->pw[s] / RT;
+        for (int b = 0; b < D; ++b) ua[b] = uc[b];
+    }
+    for (int q = 0; q < Q; ++q) {
+        if (o->e[q][a] * out >= 0) continue;
+        fw[q] = feq_q(o, cfg, q, ra, ua) + (fo[q] - feq_q(o, cfg, q, rc, uc));
+    }
+}
+
+/* Flux density xi_a f(x_b, t_n + h) of every velocity through the interface
+ * of axis a with index c[a] (normal +e_a), the integrand of Eq. (microflux)
+ * at the half step: f-bar from Eq. (gradient), the wall rule on wall
+ * interfaces, the interface moments (macro_values with G(x_b, t_n + h) and
+ * h/2), and f from f-bar by inverting Eq. (original_f):
+ * f = 2 tau/(2 tau + h) f-bar + h/(2 tau + h) feq + tau h/(2 tau + h) S. */
+static void interface_flux(const octx* o, const oracle_cfg* cfg, const double* phi, const double* Gext, double gth,
+                           int a, const int* c, double* flux)
+{
+    const int Q = o->Q;
+    const double h = 0.5 * cfg->dt, tau = cfg->tau;
+    const double b_f = 2.0 * tau / (2.0 * tau + h);
+    const double b_eq = h / (2.0 * tau + h);
+    const double b_s = tau * h / (2.0 * tau + h);
+    double fb[MAXQ], fe[MAXQ], S[MAXQ], G[3], rho, u[3];
+    interface_fbar(o, phi, a, c, h, fb);
+    const int N = o->n[a];
+    if (!o->per[a] && (c[a] == 0 || c[a] == N)) {
+        int co[3] = {c[0], c[1], c[2]};
+        co[a] = (c[a] == 0) ? 1 : N - 1;
+        double fo[MAXQ], Go[3], rc, uc[3];
+        interface_fbar(o, phi, a, co, h, fo);
+        accel_face(o, cfg, Gext, a, co, gth, Go);
+        point_macro(o, cfg, fo, Go, h / 2.0, &rc, uc);
+        wall_condition(o, cfg, 2 * a + (c[a] == N), fb, fo, rc, uc);
+    }
+    accel_face(o, cfg, Gext, a, c, gth, G);
+    point_macro(o, cfg, fb, G, h / 2.0, &rho, u);
+    point_eq(o, cfg, rho, u, G, fe, S);
+    for (int q = 0; q < Q; ++q) flux[q] = o->xi[q][a] * (b_f * fb[q] + b_eq * fe[q] + b_s * S[q]);
+}
+
+/* the step's work arrays, kept across the steps of one run */
+typedef struct {
+    double* phi;       /* f-bar-plus on the extended cell set */
+    double* Gext;      /* spatial force on the extended cell set, or NULL */
+    double* flux[3];   /* flux densities on the interfaces of each axis */
+} oworkspace;
+
+static int work_alloc(const octx* o, const double* force, oworkspace* w)
+{
+    memset(w, 0, sizeof(*w));
+    w->phi = (double*)calloc((size_t)ncells_ext(o) * o->Q, sizeof(double));
+    int ok = w->phi != NULL;
+    for (int a = 0; a < o->D; ++a) {
+        w->flux[a] = (double*)malloc(sizeof(double) * face_count(o, a) * o->Q);
+        ok = ok && w->flux[a] != NULL;
+    }
+    w->Gext = force_ext(o, force);
+    return ok ? 0 : -1;
+}
+
+static void work_free(oworkspace* w)
+{
+    free(w->phi);
+    free(w->Gext);
+    for (int a = 0; a < 3; ++a) free(w->flux[a]);
+    memset(w, 0, sizeof(*w));
+}
+
+static void step_with(const octx* o, const oracle_cfg* cfg, oworkspace* w, const double* fin, double* fout,
+                      double t)
+{
+    const int D = o->D, Q = o->Q;
+    const long nc = ncells(o);
+    const double dt = cfg->dt, h = 0.5 * dt;
     const double gt = gtime(cfg, t), gth = gtime(cfg, t + h);
 
-    double* Gext = force_ext(&o, force);
-    double* fp = (double*)calloc((size_t)nce * Q, sizeof(double)); /* f-bar-plus on X_c u X_cg */
-    double* F[3] = {NULL, NULL, NULL};                             /* values on X_b           */
-    double* Eg[3] = {NULL, NULL, NULL};                            /* f-bar-plus on X_bc      */
+    transform_cells(o, cfg, fin, w->Gext, gt, w->phi);
 
-    /* Step 1: f-bar-plus at the centres, Eq. (f_bar_+), with rho, u from
-     * Eq. (macro_values) at t_n and G(x_c, t_n). */
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int k = 0; k < o.n[2]; ++k)
-        for (int j = 0; j < o.n[1]; ++j)
-            for (int i = 0; i < o.n[0]; ++i) {
-                long ci = cell_int(&o, i, j, k), ce = cell_ext(&o, i, j, k);
-                double rho = 0.0, m[3] = {0, 0, 0}, G[3], u[3] = {0, 0, 0};
-                for (int q = 0; q < Q; ++q) {
-                    double fq = fin[q * nc + ci];
-                    rho += fq;
-                    for (int a = 0; a < D; ++a) m[a] += o.xi[q][a] * fq;
-                }
-                accel_cell(&o, cfg, Gext, ce, gt, G);
-                const double rm = mom_density(cfg, rho);
-                for (int a = 0; a < D; ++a) u[a] = (m[a] + rm * G[a] * dt / 2.0) / rm;
-                for (int q = 0; q < Q; ++q)
-                    fp[ce * Q + q] = A1 * fin[q * nc + ci] + B1 * feq_q(&o, cfg, q, rho, u) +
-                                     C1 * src_q(&o, cfg, q, rho, u, G);
-            }
-
-    /* Step 2: ghost points */
-    ghost_fill(&o, fp, Q);
-
-    /* Step 3: f-bar-plus at X_b (face mid-points) and X_bc (cross points) by
-     * centre interpolation: linear along the face normal, bilinear in the
-     * plane of the two interfaces that cross. */
     for (int a = 0; a < D; ++a) {
-        long nf = face_count(&o, a);
-        F[a] = (double*)malloc(sizeof(double) * nf * Q);
-        int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
+        const int d0 = face_dim(o, a, 0), d1 = face_dim(o, a, 1), d2 = face_dim(o, a, 2);
 #pragma omp parallel for collapse(2) schedule(static)
         for (int k = 0; k < d2; ++k)
             for (int j = 0; j < d1; ++j)
                 for (int i = 0; i < d0; ++i) {
-                    int c[3] = {i, j, k}, cl[3] = {i, j, k};
-                    cl[a] -= 1;
-                    double w = o.w[a][c[a]];
-                    long L = cell_ext(&o, cl[0], cl[1], cl[2]), R = cell_ext(&o, c[0], c[1], c[2]);
-                    long fi = face_idx(&o, a, c);
-                    for (int q = 0; q < Q; ++q)
-                        F[a][fi * Q + q] = (1.0 - w) * fp[L * Q + q] + w * fp[R * Q + q];
-                }
-    }
-    for (int a = 0; a < D; ++a)
-        for (int b = a + 1; b < D; ++b) {
-            int p = pair_id(a, b);
-            long ne = edge_count(&o, a, b);
-            Eg[p] = (double*)malloc(sizeof(double) * ne * Q);
-            int d0 = edge_dim(&o, a, b, 0), d1 = edge_dim(&o, a, b, 1), d2 = edge_dim(&o, a, b, 2);
-#pragma omp parallel for collapse(2) schedule(static)
-            for (int k = 0; k < d2; ++k)
-                for (int j = 0; j < d1; ++j)
-                    for (int i = 0; i < d0; ++i) {
-                        int c[3] = {i, j, k};
-                        double wa = o.w[a][c[a]], wb = o.w[b][c[b]];
-                        int c00[3] = {i, j, k}, c10[3] = {i, j, k}, c01[3] = {i, j, k}, c11[3] = {i, j, k};
-                        c00[a] -= 1; c00[b] -= 1;
-                        c10[b] -= 1;
-                        c01[a] -= 1;
-                        long p00 = cell_ext(&o, c00[0], c00[1], c00[2]);
-                        long p10 = cell_ext(&o, c10[0], c10[1], c10[2]);
-                        long p01 = cell_ext(&o, c01[0], c01[1], c01[2]);
-                        long p11 = cell_ext(&o, c11[0], c11[1], c11[2]);
-                        long ei = edge_idx(&o, a, b, c);
-                        for (int q = 0; q < Q; ++q) {
-                            double e1 = (1.0 - wa) * fp[p00 * Q + q] + wa * fp[p10 * Q + q];
-                            double e2 = (1.0 - wa) * fp[p01 * Q + q] + wa * fp[p11 * Q + q];
-                            Eg[p][ei * Q + q] = (1.0 - wb) * e1 + wb * e2;
-                        }
-                    }
-        }
-
-    /* Step 4: gradient sigma_b by differences and
-     * F(x_b) = f-bar-plus(x_b) - xi h . sigma_b, Eq. (gradient).
-     * Normal component: difference of the two centres; tangential
-     * components: difference of the two cross points over the face width. */
-    for (int a = 0; a < D; ++a) {
-        int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
-#pragma omp parallel for collapse(2) schedule(static)
-        for (int k = 0; k < d2; ++k)
-            for (int j = 0; j < d1; ++j)
-                for (int i = 0; i < d0; ++i) {
-                    int c[3] = {i, j, k}, cl[3] = {i, j, k};
-                    cl[a] -= 1;
-                    long L = cell_ext(&o, cl[0], cl[1], cl[2]), R = cell_ext(&o, c[0], c[1], c[2]);
-                    long fi = face_idx(&o, a, c);
-                    double gn = o.g[a][c[a]];
-                    long e_lo[3] = {0, 0, 0}, e_hi[3] = {0, 0, 0};
-                    double inv[3] = {0, 0, 0};
-                    for (int b = 0; b < D; ++b) {
-                        if (b == a) continue;
-                        int cu[3] = {i, j, k}, cd[3] = {i, j, k};
-                        cu[b] += 1;
-                        e_lo[b] = edge_idx(&o, a, b, cd);
-                        e_hi[b] = edge_idx(&o, a, b, cu);
-                        inv[b] = 1.0 / o.dl[b][c[b]];
-                    }
-                    for (int q = 0; q < Q; ++q) {
-                        double sig[3] = {0, 0, 0};
-                        sig[a] = gn * (fp[R * Q + q] - fp[L * Q + q]);
-                        for (int b = 0; b < D; ++b) {
-                            if (b == a) continue;
-                            const double* Ep = Eg[pair_id(a, b)];
-                            sig[b] = (Ep[e_hi[b] * Q + q] - Ep[e_lo[b] * Q + q]) * inv[b];
-                        }
-                        double xs = 0.0;
-                        for (int b = 0; b < D; ++b) xs += o.xi[q][b] * sig[b];
-                        F[a][fi * Q + q] = F[a][fi * Q + q] - h * xs;
-                    }
+                    const int c[3] = {i, j, k};
+                    interface_flux(o, cfg, w->phi, w->Gext, gth, a, c, w->flux[a] + face_idx(o, a, c) * Q);
                 }
     }
 
-    /* Step 5: boundary processing at wall faces, for the velocities leaving
-     * the wall into the domain (xi . n < 0, n the outward normal):
-     * bounce-back, Eq. (BB), with rho_w = rho0; or non-equilibrium
-     * extrapolation, Eq. (NEQ), whose non-equilibrium part is taken at x_c,
-     * the opposite interface of the same wall cell, with rho_c, u_c its
-     * step-6 moments.  Velocity condition: (rho_c, u_w); pressure
-     * condition: (rho0 + p_w/RT, u_c). */
-    for (int s = 0; s < 2 * D; ++s) {
-        int a = s / 2, hi = s % 2;
-        if (o.per[a]) continue;
-        int bc = cfg->bc[s];
-        int N = o.n[a];
-        int fw = hi ? N : 0, fo = hi ? N - 1 : 1;
-        int nsg = hi ? 1 : -1;
-        int lo[3] = {0, 0, 0}, up[3];
-        for (int b = 0; b < 3; ++b) up[b] = o.n[b] - 1;
-        lo[a] = up[a] = 0;
+    /* Eq. (evolution_equation) with f~+ of Eq. (f_tilde_+): the flux out of
+     * cell V through its interfaces j is sum_j (xi.n_j) f s_j; on the
+     * tensor mesh interface j of axis a has area s_a = |V| / Delta_a */
 #pragma omp parallel for collapse(2) schedule(static)
-        for (int k = lo[2]; k <= up[2]; ++k)
-            for (int j = lo[1]; j <= up[1]; ++j)
-                for (int i = lo[0]; i <= up[0]; ++i) {
-                    int cw[3] = {i, j, k}, co[3] = {i, j, k};
-                    cw[a] = fw; co[a] = fo;
-                    double* Fw = F[a] + face_idx(&o, a, cw) * Q;
-                    const double* Fo = F[a] + face_idx(&o, a, co) * Q;
-                    double pre[MAXQ];
-                    for (int q = 0; q < Q; ++q) pre[q] = Fw[q];
-                    if (bc == OR_BOUNCE_BACK) {
-                        for (int q = 0; q < Q; ++q) {
-                            if (o.e[q][a] * nsg >= 0) continue;
-                            double xu = 0.0;
-                            for (int b = 0; b < D; ++b) xu += o.xi[q][b] * cfg->uw[s][b];
-                            Fw[q] = pre[o.opp[q]] + 2.0 * rho0 * o.W[q] * xu / RT;
-                        }
-                    } else {
-                        double rc = 0.0, m[3] = {0, 0, 0}, Gb[3], uc[3] = {0, 0, 0};
-                        for (int q = 0; q < Q; ++q) {
-                            rc += Fo[q];
-                            for (int b = 0; b < D; ++b) m[b] += o.xi[q][b] * Fo[q];
-                        }
-                        accel_face(&o, cfg, Gext, a, co, gth, Gb);
-                        const double rm = mom_density(cfg, rc);
-                        for (int b = 0; b < D; ++b) uc[b] = (m[b] + rm * Gb[b] * h / 2.0) / rm;
-                        double ra, ua[3] = {0, 0, 0};
-                        if (bc == OR_NEQ_VELOCITY) {
-                            ra = rc;
-                            for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
-                        } else {
-                            ra = rho0 + cfg->pw[s] / RT;
-                            for (int b = 0; b < D; ++b) ua[b] = uc[b];
-                        }
-                        for (int q = 0; q < Q; ++q) {
-                            if (o.e[q][a] * nsg >= 0) continue;
-                            Fw[q] = feq_q(&o, cfg, q, ra, ua) + (Fo[q] - feq_q(&o, cfg, q, rc, uc));
-                        }
-                    }
-                }
-    }
-
-    /* Steps 6-7: interface moments (with + rho0 G h/2) and the original
-     * distribution f(x_b, t_n + h), inverse of Eq. (original_f). */
-    for (int a = 0; a < D; ++a) {
-        int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
-#pragma omp parallel for collapse(2) schedule(static)
-        for (int k = 0; k < d2; ++k)
-            for (int j = 0; j < d1; ++j)
-                for (int i = 0; i < d0; ++i) {
-                    int c[3] = {i, j, k};
-                    double* Fb = F[a] + face_idx(&o, a, c) * Q;
-                    double rho = 0.0, m[3] = {0, 0, 0}, G[3], u[3] = {0, 0, 0};
-                    for (int q = 0; q < Q; ++q) {
-                        rho += Fb[q];
-                        for (int b = 0; b < D; ++b) m[b] += o.xi[q][b] * Fb[q];
-                    }
-                    accel_face(&o, cfg, Gext, a, c, gth, G);
-                    const double rm = mom_density(cfg, rho);
-                    for (int b = 0; b < D; ++b) u[b] = (m[b] + rm * G[b] * h / 2.0) / rm;
-                    for (int q = 0; q < Q; ++q)
-                        Fb[q] = A7 * Fb[q] + B7 * feq_q(&o, cfg, q, rho, u) + C7 * src_q(&o, cfg, q, rho, u, G);
-                }
-    }
-
-    /* Steps 8-9: micro-flux m = sum over the cell's faces of (xi.n_j) F s_j,
-     * Eq. (microflux) at t_n + h, then f~+ = 4/3 f-bar-plus - 1/3 f~
-     * (Eq. (f_tilde_+)) and f~(t+dt) = f~+ - dt/|V| m (Eq. (evolution_equation)). */
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int k = 0; k < o.n[2]; ++k)
-        for (int j = 0; j < o.n[1]; ++j)
-            for (int i = 0; i < o.n[0]; ++i) {
-                int c[3] = {i, j, k};
-                long ci = cell_int(&o, i, j, k), ce = cell_ext(&o, i, j, k);
+    for (int k = 0; k < o->n[2]; ++k)
+        for (int j = 0; j < o->n[1]; ++j)
+            for (int i = 0; i < o->n[0]; ++i) {
+                const int c[3] = {i, j, k};
+                const long ci = cell_int(o, i, j, k), ce = cell_ext(o, i, j, k);
                 double V = 1.0, s[3] = {1, 1, 1};
-                for (int a = 0; a < D; ++a) V *= o.dl[a][c[a]];
+                for (int a = 0; a < D; ++a) V *= o->dl[a][c[a]];
                 for (int a = 0; a < D; ++a)
                     for (int b = 0; b < D; ++b)
-                        if (b != a) s[a] *= o.dl[b][c[b]];
-                long fpl[3], fmi[3];
+                        if (b != a) s[a] *= o->dl[b][c[b]];
+                const double* up[3] = {NULL, NULL, NULL};
+                const double* dn[3] = {NULL, NULL, NULL};
                 for (int a = 0; a < D; ++a) {
                     int cp[3] = {i, j, k};
                     cp[a] += 1;
-                    fmi[a] = face_idx(&o, a, c);
-                    fpl[a] = face_idx(&o, a, cp);
+                    dn[a] = w->flux[a] + face_idx(o, a, c) * Q;
+                    up[a] = w->flux[a] + face_idx(o, a, cp) * Q;
                 }
                 for (int q = 0; q < Q; ++q) {
                     double m = 0.0;
-                    for (int a = 0; a < D; ++a) {
-                        m += o.xi[q][a] * F[a][fpl[a] * Q + q] * s[a];   /* n = +e_a */
-                        m += -o.xi[q][a] * F[a][fmi[a] * Q + q] * s[a];  /* n = -e_a */
-                    }
-                    double ftp = 4.0 / 3.0 * fp[ce * Q + q] - 1.0 / 3.0 * fin[q * nc + ci];
+                    for (int a = 0; a < D; ++a) m += (up[a][q] - dn[a][q]) * s[a];
+                    const double ftp = 4.0 / 3.0 * w->phi[ce * Q + q] - 1.0 / 3.0 * fin[q * nc + ci];
                     fout[q * nc + ci] = ftp - dt / V * m;
                 }
             }
+}
 
-    for (int a = 0; a < 3; ++a) { free(F[a]); free(Eg[a]); }
-    free(fp);
-    free(Gext);
+int oracle_step(const oracle_cfg* cfg, const double* fin, double* fout, const double* force, double t)
+{
+    return oracle_run(cfg, fin, fout, force, t, 1);
+}
+
+/* nsteps steps from t0 (time t0 + i dt at step i), f_in -> f_out; f_out may
+ * equal f_in */
+int oracle_run(const oracle_cfg* cfg, const double* fin, double* fout, const double* force, double t0,
+               int nsteps)
+{
+    octx o;
+    if (nsteps < 0) return -1;
+    if (setup(&o, cfg)) return -1;
+    oworkspace w;
+    const size_t len = (size_t)ncells(&o) * o.Q;
+    double* tmp = (double*)malloc(sizeof(double) * len);
+    if (work_alloc(&o, force, &w) || !tmp) {
+        work_free(&w);
+        free(tmp);
+        ctx_free(&o);
+        return -1;
+    }
+    if (fout != fin) memcpy(fout, fin, sizeof(double) * len);
+    double t = t0;
+    for (int s = 0; s < nsteps; ++s) {
+        step_with(&o, cfg, &w, fout, tmp, t);
+        memcpy(fout, tmp, sizeof(double) * len);
+        t += cfg->dt;
+    }
+    free(tmp);
+    work_free(&w);
+    ctx_free(&o);
+    return 0;
+}
+
+/* f-bar(x_b, t_n + h) on every interface of axis `axis` before the wall
+ * rules, from given f-bar-plus values phi[q][cells] at the centres (ghosts
+ * by the same rule as in the step): the interface reconstruction of
+ * Eq. (gradient) on its own, for tests.  out[q][faces] with the interface
+ * layout of axis `axis` ([z][y][x], n+1 along the axis). */
+int oracle_interface_values(const oracle_cfg* cfg, int axis, const double* phi_cells, double* out)
+{
+    octx o;
+    if (setup(&o, cfg)) return -1;
+    if (axis < 0 || axis >= o.D) { ctx_free(&o); return -1; }
+    const int Q = o.Q;
+    const long nc = ncells(&o), nf = face_count(&o, axis);
+    double* phi = (double*)calloc((size_t)ncells_ext(&o) * Q, sizeof(double));
+    for (int k = 0; k < o.n[2]; ++k)
+        for (int j = 0; j < o.n[1]; ++j)
+            for (int i = 0; i < o.n[0]; ++i)
+                for (int q = 0; q < Q; ++q)
+                    phi[cell_ext(&o, i, j, k) * Q + q] = phi_cells[q * nc + cell_int(&o, i, j, k)];
+    ghost_fill(&o, phi, Q);
+    const double h = 0.5 * cfg->dt;
+    const int d0 = face_dim(&o, axis, 0), d1 = face_dim(&o, axis, 1), d2 = face_dim(&o, axis, 2);
+    for (int k = 0; k < d2; ++k)
+        for (int j = 0; j < d1; ++j)
+            for (int i = 0; i < d0; ++i) {
+                const int c[3] = {i, j, k};
+                double fb[MAXQ];
+                interface_fbar(&o, phi, axis, c, h, fb);
+                for (int q = 0; q < Q; ++q) out[q * nf + face_idx(&o, axis, c)] = fb[q];
+            }
+    free(phi);
     ctx_free(&o);
     return 0;
 }
 
 /* ------------------------------------------------------------------------ */
-/* step 10 / outputs: Eq. (macro_values), p = (rho - rho0) RT (gauge        */
-/* pressure, both models)                                                    */
+/* outputs: Eq. (macro_values) at t, p = (rho - rho0) RT (gauge pressure,   */
+/* both models)                                                              */
 /* ------------------------------------------------------------------------ */
 int oracle_moments(const oracle_cfg* cfg, const double* f, const double* force, double t,
                    double* rho, double* u, double* p, double* totals)
@@ -761,9 +862,10 @@ static void feq_partials(const octx* o, const oracle_cfg* cfg, int q, double rho
 
 static inline int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
-/* Step 3 (cross points) and step 4 for one face value: F(x_b) for velocity
- * q on the face of axis a with coordinates c (c[a] = face index), written
- * out as in the forward step; the reverse scatter below is its transpose. */
+/* Eq. (gradient) for one velocity q on the interface of axis a with
+ * coordinates c (c[a] = interface index): the same value as interface_fbar,
+ * written with the bilinear weights explicit so that face_value_adj below is
+ * visibly its transpose. */
 static double face_value(const octx* o, const double* fp, int a, const int* c, int q, double h)
 {
     const int D = o->D, Q = o->Q;
@@ -868,7 +970,8 @@ static void ghost_fold(const octx* o, double* v, int ncomp)
     }
 }
 
-/* moments of a face value set at time factor gth (steps 6, model 0) */
+/* interface moments of a set of f-bar values (Eq. (macro_values) with G at
+ * the interface and h/2; model 0) */
 static void face_macro(const octx* o, const oracle_cfg* cfg, const double* Fb, const double* G, double h,
                        double* rho, double* u)
 {
@@ -884,12 +987,13 @@ static void face_macro(const octx* o, const oracle_cfg* cfg, const double* Fb, c
 
 /* Reverse mode of one step (incompressible model) on any mesh and boundary
  * set: the forward intermediates are recomputed (no tape), then every step
- * of the forward is transposed in reverse order: the update (steps 8-9),
- * the original distribution at the faces (step 7 with the step-6 moments),
- * the wall rules (step 5: bounce-back is a permutation plus a constant; the
+ * of the forward is transposed in reverse order: the cell update
+ * (Eqs. (f_tilde_+), (evolution_equation)), the original distribution at the
+ * interfaces (inverse of Eq. (original_f) with the interface moments), the
+ * wall rules (Eq. (BB) is a permutation plus a constant; the
  * NEQ rules depend on the moments and values of the opposite interface of
- * the wall cell), the reconstruction (steps 3-4), the ghost points (step 2)
- * and Eq. (f_bar_+) with the macroscopic recovery (step 1).  Face n of a
+ * the wall cell), the reconstruction (Eq. (gradient)), the ghost layer and
+ * Eq. (f_bar_+) with the macroscopic recovery (Eq. (macro_values)).  Face n of a
  * periodic axis is computed by the forward step as a face of its own (equal
  * to face 0), and is transposed as one. */
 int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* force, double t,
@@ -909,7 +1013,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
     const double C7 = tau * h / (2.0 * tau + h);
     const double gt = gtime(cfg, t), gth = gtime(cfg, t + h);
 
-    /* ---- forward recomputation: step 1, step 2, steps 3-4, step 5 ---- */
+    /* ---- forward recomputation: cell transform, ghosts, reconstruction, wall rules ---- */
     double* Gext = force_ext(&o, force);
     double* fp = (double*)calloc((size_t)nce * Q, sizeof(double));
     double* rho_c = (double*)calloc((size_t)nc, sizeof(double));
@@ -935,7 +1039,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
             }
     ghost_fill(&o, fp, Q);
 
-    /* F4: face values after step 4; F5: after the wall rules of step 5 */
+    /* F4: f-bar on the interfaces from Eq. (gradient); F5: after the wall rules */
     double* F4[3] = {NULL, NULL, NULL};
     double* F5[3] = {NULL, NULL, NULL};
     double* Fb5[3] = {NULL, NULL, NULL}; /* adjoint of F5, then of F4 */
@@ -1006,7 +1110,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
     double* Gb_sp = (double*)calloc((size_t)nce * 3, sizeof(double)); /* adjoint of the spatial force (ext) */
     for (long c = 0; c < nc * Q; ++c) lam_out[c] = 0.0;
 
-    /* steps 8-9: f~new = 4/3 f-bar-plus - 1/3 f~ - dt/V sum_faces (xi.n) F s */
+    /* Eqs. (f_tilde_+), (evolution_equation): f~new = 4/3 f-bar-plus - 1/3 f~ - dt/V sum_faces (xi.n) f s */
     for (int k = 0; k < o.n[2]; ++k)
         for (int j = 0; j < o.n[1]; ++j)
             for (int i = 0; i < o.n[0]; ++i) {
@@ -1017,7 +1121,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                 }
             }
 
-    /* step 7 at every face, from the flux adjoint of its (at most two) cells */
+    /* inverse of Eq. (original_f) at every interface, from the flux adjoint of its (at most two) cells */
     for (int a = 0; a < D; ++a) {
         int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
         int N = o.n[a];
@@ -1066,7 +1170,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                 }
     }
 
-    /* step 5 transposed: Fb5 of wall faces becomes the adjoint of F4; NEQ
+    /* wall rules transposed: Fb5 of wall faces becomes the adjoint of F4; NEQ
      * adds to the opposite interface of the wall cell */
     for (int s = 0; s < 2 * D; ++s) {
         int a = s / 2, hi = s % 2;
@@ -1130,7 +1234,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                 }
     }
 
-    /* steps 3-4 transposed, and the face acceleration (interpolated like
+    /* Eq. (gradient) transposed, and the face acceleration (interpolated like
      * f-bar-plus along the normal, at t_n + h) */
     for (int a = 0; a < D; ++a) {
         int d0 = face_dim(&o, a, 0), d1 = face_dim(&o, a, 1), d2 = face_dim(&o, a, 2);
@@ -1150,7 +1254,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                 }
     }
 
-    /* step 2 transposed (f-bar-plus and the spatial force share the rule;
+    /* ghost layer transposed (f-bar-plus and the spatial force share the rule;
      * the force adjoint is kept with 3 components per point) */
     ghost_fold(&o, fpb, Q);
     {
@@ -1163,7 +1267,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
         free(g);
     }
 
-    /* step 1 transposed */
+    /* Eq. (f_bar_+) with Eq. (macro_values) transposed */
     for (int k = 0; k < o.n[2]; ++k)
         for (int j = 0; j < o.n[1]; ++j)
             for (int i = 0; i < o.n[0]; ++i) {

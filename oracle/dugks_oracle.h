@@ -7,11 +7,14 @@
  * baseline leg of the benchmark load it.  It shares no source, header, table
  * or helper with the HIP implementation.
  *
- * The step follows the Appendix algorithm (steps 1-10) literally, over the
- * explicit point sets X_c (cell centres), X_cg (ghost centres), X_b (face
- * mid-points) and X_bc (interface cross points: 2-D corners, 3-D edge
- * mid-points).  Where the paper is silent or garbled, the reading taken is
- * stated at the code that applies it.
+ * The step is written from the equations of Sec. II: a transform of every
+ * cell centre (Eqs. (macro_values), (f_bar_+)) with a ghost layer on wall
+ * axes, one flux evaluation per interface (Eq. (gradient) with cross-point
+ * values for the tangential differences, Eqs. (BB)/(NEQ) on walls, the
+ * interface moments, the inverse of Eq. (original_f), Eq. (microflux)), and
+ * the conservative cell update (Eqs. (f_tilde_+), (evolution_equation)).
+ * Where the paper is silent or garbled, the reading taken is stated at the
+ * code that applies it.
  *
  * Array layout at the interface (same as the product's, documented there):
  *   distributions  f[q][z][y][x]  (x fastest), q in the lattice order below
@@ -29,7 +32,7 @@ enum { OR_PERIODIC = 0, OR_NEQ_VELOCITY = 1, OR_NEQ_PRESSURE = 2, OR_BOUNCE_BACK
 enum { OR_UNIFORM = 0, OR_TANH = 1 };
 
 typedef struct {
-    int lattice;        /* 9 (D2Q9) or 19 (D3Q19) */
+    int lattice;        /* 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27) */
     int n[3];           /* cells per axis, n[2] == 1 for D2Q9 */
     double L[3];        /* domain length per axis */
     int mesh[3];        /* OR_UNIFORM or OR_TANH per axis */
@@ -63,6 +66,18 @@ int oracle_init(const oracle_cfg* cfg, const double* rho, const double* u,
 /* one step t_n -> t_n + dt; force nullable (spatial part G^(x), [D][cells]) */
 int oracle_step(const oracle_cfg* cfg, const double* f_in, double* f_out,
                 const double* force, double t_n);
+
+/* nsteps steps from t0 (step i at t0 + i dt); f_out may equal f_in */
+int oracle_run(const oracle_cfg* cfg, const double* f_in, double* f_out,
+               const double* force, double t0, int nsteps);
+
+/* the interface reconstruction of Eq. (gradient) on its own (for tests):
+ * f-bar(x_b, t_n + h) on every interface of one axis, before wall rules,
+ * from given f-bar-plus values phi[q][cells] at the cell centres (ghost
+ * values by the step's extrapolation rule).  out[q][interfaces], interfaces
+ * laid out [z][y][x] with n+1 along `axis` */
+int oracle_interface_values(const oracle_cfg* cfg, int axis, const double* phi,
+                            double* out);
 
 /* rho, u (D comps), p at time t; each output nullable.
  * totals (nullable, 6): sum V rho, sum V j_x, sum V j_y, sum V j_z,
