@@ -196,6 +196,11 @@ void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& me
     P.C1 = (T)(3.0 * tau * h / (2.0 * tau + dt));
     P.B7 = (T)(h / (2.0 * tau + h));
     P.C7 = (T)(tau * h / (2.0 * tau + h));
+    {
+        const double b1 = 3.0 * h / (2.0 * tau + dt);
+        P.bu_ok = std::fabs(1.0 - b1) >= 0.25 ? 1 : 0;
+        P.Bu = P.bu_ok ? (T)(b1 / (3.0 * (1.0 - b1))) : T(0);
+    }
     for (int a = 0; a < 3; ++a) P.G0[a] = (T)(a < D ? c->G[a] : 0.0);
     {
         const double cc = std::sqrt(3.0 * c->RT), RT = c->RT, r0 = c->rho0;

@@ -50,6 +50,13 @@ struct Inst {
     T rho0, RT, c, h, dt;
     T B1, C1;      // Eq. (f_bar_+) in deviation form: phi = f + B1 (feq - f) + C1 S
     T B7, C7;      // step 7:  f = fbar + B7 (feq - fbar) + C7 S
+    // update without the cell's own state (no acceleration):
+    // f~(n+1) = phi + Bu (feq - phi) - fluxes, Bu = B1 / (3 (1 - B1)), from
+    // Eq. (f_tilde_+) with f~ = (phi - B1 feq) / (1 - B1).  Bu has a pole at
+    // B1 = 1 (dt = 4 tau) and multiplies the rounding of feq - phi by
+    // 1/(1 - B1), so the form is allowed (bu_ok = 1) only for |1 - B1| >= 1/4
+    T Bu;
+    int bu_ok;
     T G0[3];
     // point-formula constants (host-computed): c / rho0, 1 / RT and the
     // factored Eqs. (icfeq), (S): eqH = rho0 / (2 RT), eqB = rho0 c / RT,

@@ -403,10 +403,12 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // D3Q19 (4 waves per SIMD, 128 registers) spends the freed own-state
     // registers on the late prefetch; D3Q27, which keeps no own state in
     // registers, saves the second read of it (FP32 also takes the prefetch,
-    // FP64 has no registers for it).
+    // FP64 has no registers for it).  The host launches these instances only
+    // where |1 - B1| >= 1/4 (Inst::bu_ok); elsewhere it takes the instance
+    // with the acceleration terms, whose skipped terms are exact zeros.
     constexpr bool PHIU = NOG && !ORIG && LPF && ((LAT::Q == 19 && sizeof(T) == 4) || LAT::Q == 27);
     constexpr bool OWNR = OWN && !PHIU;
-    const T Bu = P.B1 / (T(3) * (T(1) - P.B1));
+    const T Bu = P.Bu;
     T* fxb = lds + 3 * Q * SQ;   // [2][NX][BY][BX] upper x faces, per half
     T* fyb = fxb + 2 * NX * SQ;  // [2][NY][BY][BX] upper y faces (3-D)
     // D2Q9: the force field of the ring planes, [3][D][BY][BX], after the
@@ -879,8 +881,13 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
     // tiles per CU) without spills
     constexpr int MINW_UF = (LAT::Q == 19 && sizeof(T) == 4) ? 4 : MINW;
     // no acceleration at all (G = 0, no field): instances without the
-    // source term of Eq. (S) (bitwise the same results, fewer operations)
-    const bool nog = !force && P.G0[0] == T(0) && P.G0[1] == T(0) && P.G0[2] == T(0);
+    // source term of Eq. (S) (bitwise the same results, fewer operations).
+    // Those of FP32 D3Q19 and of D3Q27 update without the own state, whose
+    // coefficient B1 / (3 (1 - B1)) is allowed only away from its pole at
+    // B1 = 1; near it the instance with the acceleration terms runs instead
+    constexpr bool phiu_lat = (LAT::Q == 19 && sizeof(T) == 4) || LAT::Q == 27;
+    const bool nog = !force && P.G0[0] == T(0) && P.G0[1] == T(0) && P.G0[2] == T(0) &&
+                     (P.orig || !phiu_lat || P.bu_ok);
     if (P.orig) {
         // the original-model equilibrium (launches without a force field;
         // without acceleration the source-free instances, bitwise the same)
