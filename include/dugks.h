@@ -233,6 +233,25 @@ int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, doubl
                        const void* lam_np1, void* lam_n, void* grad_force, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as dugks_step_adjoint, with the scratch
+ * taken from a static device area of 64 MiB (each GPU the library runs on
+ * holds it until the process ends) instead of the context's lazily
+ * allocated buffer.  The call allocates and frees nothing.  The caller still
+ * owns every input and output.  A problem whose scratch exceeds 64 MiB is
+ * rejected with DUGKS_EINVAL (the message states both sizes; 64 MiB holds
+ * the 256^2 D2Q9 FP64 adjoint, periodic or with walls).  The current device
+ * must be the one the context was created on.  Every call on one GPU
+ * shares that GPU's area and every element the kernels read is written
+ * earlier in the same call, so nothing needs clearing; calls that overlap
+ * on one GPU (other streams, other threads, other contexts) race.
+ * Asynchronous.
+ */
+int dugks_step_adjoint_static(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
+                              const void* lam_np1, void* lam_n, void* grad_force, void* stream);
+
+/*
  * Reverse mode of the initial state with rho = rho0:
  *   grad_u     += (d f0 / d u)^T lam0   (nullable, [D])
  *   grad_force += (d f0 / d G^)^T lam0  (nullable, [D])

@@ -90,6 +90,7 @@ def load():
     lib.dugks_totals_async.argtypes = [_VP, _VP, _VP, D, _VP, _VP]
     lib.dugks_velocity_change.argtypes = [_VP, _VP, _VP, _VP, D, D, ctypes.POINTER(D), _VP]
     lib.dugks_step_adjoint.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
+    lib.dugks_step_adjoint_static.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_init_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP, _VP]
     lib.dugks_moments_vjp.argtypes = [_VP, _VP, _VP, D, _VP, _VP, _VP]
     lib.dugks_kernel_variant.argtypes = [_VP]
@@ -227,6 +228,13 @@ def dugks_velocity_change(ctx, f_a, f_b, force=None, t_a=0.0, t_b=0.0, stream=No
 def dugks_step_adjoint(ctx, f_n, lam_np1, lam_n, force=None, t_n=0.0, grad_force=None, stream=None):
     _check(load().dugks_step_adjoint(_VP(ctx), _ptr(f_n), _ptr(force), float(t_n), _ptr(lam_np1), _ptr(lam_n),
                                      _ptr(grad_force), _stream(stream)), _VP(ctx))
+
+
+def dugks_step_adjoint_static(ctx, f_n, lam_np1, lam_n, force=None, t_n=0.0, grad_force=None, stream=None):
+    """dugks_step_adjoint with its scratch in the library's static device
+    area (no device allocation; problems up to 64 MiB of scratch)"""
+    _check(load().dugks_step_adjoint_static(_VP(ctx), _ptr(f_n), _ptr(force), float(t_n), _ptr(lam_np1),
+                                            _ptr(lam_n), _ptr(grad_force), _stream(stream)), _VP(ctx))
 
 
 def dugks_init_vjp(ctx, lam0, u=None, force=None, t0=0.0, grad_u=None, grad_force=None, stream=None):

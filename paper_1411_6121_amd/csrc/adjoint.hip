@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 #include <utility>
 
 #include "ctx.hpp"
@@ -936,9 +937,71 @@ __global__ __launch_bounds__(256) void k_adjw_cell(const Inst<T>* __restrict__ P
 
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 
+// Scratch of the allocation-free adjoint (dugks_step_adjoint_static): one
+// static device area, which every GPU the library runs on holds until the
+// process ends.  Host code never uses the array's name as a device address:
+// its per-device address comes from hipGetSymbolAddress, looked up once per
+// device with that device current (at dugks_init, else at the entry
+// point's first call there) and kept in static_scratch_dev.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static void* static_scratch_dev[kMaxDevices];
+static std::mutex static_scratch_mu;
+
+static hipError_t static_scratch_lookup(int dev, void** out)
+{
+    std::lock_guard<std::mutex> lock(static_scratch_mu);
+    if (!static_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        static_scratch_dev[dev] = p;
+    }
+    *out = static_scratch_dev[dev];
+    return hipSuccess;
+}
+
+void adjoint_static_setup()
+{
+    int dev = -1;
+    void* p = nullptr;
+    // a failed lookup is retried (and reported) by the entry point
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) (void)static_scratch_lookup(dev, &p);
+}
+
+// device scratch of `need` bytes for one adjoint step: the context's own
+// buffer (allocated on first use, grown when needed), or the static area
+static int adjoint_scratch(dugks_ctx* ctx, size_t need, bool stat, void** out)
+{
+    if (stat) {
+        if (need > kStaticScratchBytes)
+            return fail(ctx, DUGKS_EINVAL,
+                        "the adjoint step needs " + std::to_string(need) +
+                            " bytes of scratch, more than the static area of the allocation-free entry point (" +
+                            std::to_string(kStaticScratchBytes) + " bytes); use dugks_step_adjoint");
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_check(ctx, e, "current device");
+        if (dev != ctx->device) return fail(ctx, DUGKS_EINVAL, "the current device is not the context's device");
+        if (dev < 0 || dev >= kMaxDevices) return fail(ctx, DUGKS_EUNSUPPORTED, "device ordinal out of range");
+        e = static_scratch_lookup(dev, out);
+        return hip_check(ctx, e, "static scratch address");
+    }
+    if (ctx->adj_bytes < need) {
+        if (ctx->adj) (void)hipFree(ctx->adj);
+        ctx->adj = nullptr;
+        ctx->adj_bytes = 0;
+        if (hipMalloc(&ctx->adj, need) != hipSuccess) return fail(ctx, DUGKS_ENOMEM, "adjoint scratch allocation failed");
+        ctx->adj_bytes = need;
+    }
+    *out = ctx->adj;
+    return DUGKS_OK;
+}
+
 template <class LAT, typename T>
 static int adjoint_step(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const void* force, double t,
-                        const void* lam_np1, void* lam_n, void* grad_force, hipStream_t st)
+                        const void* lam_np1, void* lam_n, void* grad_force, hipStream_t st, bool stat)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const size_t es = sizeof(T);
@@ -947,14 +1010,10 @@ static int adjoint_step(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const 
                         + (size_t)D * D * P.nc * es          // face force adjoints
                         + (size_t)Q * P.nc * es              // phi_hat partial
                         + (size_t)D * Q * P.nc * es;         // d_hat
-    if (ctx->adj_bytes < need) {
-        if (ctx->adj) (void)hipFree(ctx->adj);
-        ctx->adj = nullptr;
-        ctx->adj_bytes = 0;
-        if (hipMalloc(&ctx->adj, need) != hipSuccess) return fail(ctx, DUGKS_ENOMEM, "adjoint scratch allocation failed");
-        ctx->adj_bytes = need;
-    }
-    T* base = (T*)ctx->adj;
+    void* work = nullptr;
+    const int src = adjoint_scratch(ctx, need, stat, &work);
+    if (src != DUGKS_OK) return src;
+    T* base = (T*)work;
     T* phi = base;
     T* fa = phi + (size_t)P.ne * Q;
     T* ga = fa + (size_t)D * Q * P.nc;
@@ -976,7 +1035,7 @@ static int adjoint_step(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const 
 
 template <class LAT, typename T>
 static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const void* force, double t,
-                              const void* lam_np1, void* lam_n, void* grad_force, hipStream_t st)
+                              const void* lam_np1, void* lam_n, void* grad_force, hipStream_t st, bool stat)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const size_t es = sizeof(T);
@@ -993,14 +1052,10 @@ static int adjoint_step_walls(dugks_ctx* ctx, const Inst<T>& P, const void* fn, 
                         + (size_t)D * P.ne * Q * es  // d_hat (extended)
                         + (size_t)P.ne * D * es      // force adjoint (extended)
                         + (size_t)P.nc * (Q + D) * es; // phi_hat and force adjoint gathered per cell
-    if (ctx->adj_bytes < need) {
-        if (ctx->adj) (void)hipFree(ctx->adj);
-        ctx->adj = nullptr;
-        ctx->adj_bytes = 0;
-        if (hipMalloc(&ctx->adj, need) != hipSuccess) return fail(ctx, DUGKS_ENOMEM, "adjoint scratch allocation failed");
-        ctx->adj_bytes = need;
-    }
-    T* p = (T*)ctx->adj;
+    void* work = nullptr;
+    const int src = adjoint_scratch(ctx, need, stat, &work);
+    if (src != DUGKS_OK) return src;
+    T* p = (T*)work;
     T* phi = p;
     p += (size_t)P.ne * Q;
     AdjFaces AF{};
@@ -1084,8 +1139,11 @@ void release_adjoint(dugks_ctx* ctx)
 
 using namespace dugks;
 
-extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
-                                  const void* lam_np1, void* lam_n, void* grad_force, void* stream)
+namespace dugks {
+// checks and kernel choice shared by dugks_step_adjoint and its
+// allocation-free variant (stat: scratch in the static area)
+static int step_adjoint_any(dugks_ctx* ctx, const void* f_n, const void* force, double t_n, const void* lam_np1,
+                            void* lam_n, void* grad_force, void* stream, bool stat)
 {
     if (!ctx) return fail(nullptr, DUGKS_EINVAL, "null context");
     if (!f_n || !lam_np1 || !lam_n) return fail(ctx, DUGKS_EINVAL, "null buffer");
@@ -1103,19 +1161,34 @@ extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* f
     if (!periodic || (gen && gen[0] == '1')) {
         if (ctx->cfg.lattice == DUGKS_D2Q9) {
             if (ctx->cfg.dtype == DUGKS_F64)
-                return adjoint_step_walls<D2Q9, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
-            return adjoint_step_walls<D2Q9, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+                return adjoint_step_walls<D2Q9, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
+            return adjoint_step_walls<D2Q9, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
         }
         if (ctx->cfg.dtype == DUGKS_F64)
-            return adjoint_step_walls<D3Q19, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
-        return adjoint_step_walls<D3Q19, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+            return adjoint_step_walls<D3Q19, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
+        return adjoint_step_walls<D3Q19, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
     }
     if (ctx->cfg.lattice == DUGKS_D2Q9) {
-        if (ctx->cfg.dtype == DUGKS_F64) return adjoint_step<D2Q9, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
-        return adjoint_step<D2Q9, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+        if (ctx->cfg.dtype == DUGKS_F64)
+            return adjoint_step<D2Q9, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
+        return adjoint_step<D2Q9, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
     }
-    if (ctx->cfg.dtype == DUGKS_F64) return adjoint_step<D3Q19, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
-    return adjoint_step<D3Q19, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st);
+    if (ctx->cfg.dtype == DUGKS_F64)
+        return adjoint_step<D3Q19, double>(ctx, ctx->pd, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
+    return adjoint_step<D3Q19, float>(ctx, ctx->pf, f_n, force, t_n, lam_np1, lam_n, grad_force, st, stat);
+}
+}  // namespace dugks
+
+extern "C" int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
+                                  const void* lam_np1, void* lam_n, void* grad_force, void* stream)
+{
+    return step_adjoint_any(ctx, f_n, force, t_n, lam_np1, lam_n, grad_force, stream, false);
+}
+
+extern "C" int dugks_step_adjoint_static(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
+                                         const void* lam_np1, void* lam_n, void* grad_force, void* stream)
+{
+    return step_adjoint_any(ctx, f_n, force, t_n, lam_np1, lam_n, grad_force, stream, true);
 }
 
 extern "C" int dugks_init_vjp(dugks_ctx* ctx, const void* u, const void* force, double t0, const void* lam0,

@@ -24,6 +24,7 @@ struct dugks_ctx {
     int fast = 0;                 // fused-kernel variant selected at init (0 = none)
     int chunk = 0;                // planes marched per workgroup (0 = automatic)
     int n_cu = 0;                 // compute units of the device the context was created on
+    int device = -1;              // ordinal of that device
     void* adj = nullptr;          // adjoint scratch (device, lazily)
     size_t adj_bytes = 0;
 };
@@ -38,4 +39,7 @@ int fast_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, do
               bool* handled);
 void release_fast(dugks_ctx* ctx);
 void release_adjoint(dugks_ctx* ctx);
+// address of the allocation-free adjoint's static scratch on the current
+// device, looked up once per device (called by dugks_init)
+void adjoint_static_setup();
 }  // namespace dugks

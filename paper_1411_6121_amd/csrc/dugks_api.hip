@@ -545,7 +545,9 @@ extern "C" int dugks_init(const dugks_config* cfg, const void* rho, const void* 
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             ctx->n_cu = 0;
+        ctx->device = dev;
     }
+    dugks::adjoint_static_setup();
     ctx->cfg = *cfg;
     ctx->D = cfg->lattice == DUGKS_D2Q9 ? 2 : 3;
     ctx->Q = cfg->lattice;
