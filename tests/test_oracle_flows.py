@@ -154,31 +154,44 @@ def test_womersley_force_driven():
     assert errs[1] < 2e-2
 
 
-def test_periodic_flow_second_order_and_table():
-    # Eq. (PF_AS) with its body force, small fixed dt as in the paper;
-    # errors fall at second order (both meshes compared at t = 3).  The
-    # printed Table EC_VP (tests/golden/table_ec_vp.txt) is compared loosely:
-    # this reading's viscous operator in the small-dt limit is the wide
-    # central stencil, whose error constant is about 4x the printed one.
+def _recipe_rows():
     import os
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table_ec_vp_recipe.txt")) as fh:
+        for ln in fh:
+            if ln.strip() and not ln.startswith("#"):
+                v = ln.split()
+                rows[int(v[0])] = dict(eu=float(v[3]), ep=float(v[4]), ru=float(v[6]), rp=float(v[7]))
+    return rows
+
+
+def test_periodic_flow_table_recipe():
+    # Table EC_VP at the paper's recipe (Sec. III.A): Eq. (PF_AS) with its
+    # body force, dt = 1e-4, run to the relative velocity change of 1e-6 per
+    # 1000 steps; E(u) and E(p) against Eq. (PF_AS).  Both fall at second
+    # order from N = 16 to 32, and their ratios to the printed values stay
+    # within 20 % of the ratios recorded at the recipe for N = 16, 32 and 64
+    # (tests/golden/table_ec_vp_recipe.txt, written by the oracle through
+    # tests/golden/table_ec_vp_recipe.py): about 5.3-6.5 for E(u) and
+    # 3.6-6.2 for E(p).  The error is a pure amplitude error of the steady
+    # field (+5.2 % at N = 16): with dt << tau the interface term h xi.sigma
+    # of Eq. (gradient) vanishes and the interface value is the mean of the
+    # two cells, so the viscous operator is the wide central stencil, whose
+    # amplitude error (k dx)^2 / 3 = 5.1 % at N = 16 is four times that of
+    # the compact stencil the printed magnitudes correspond to.
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import table_ec_vp_recipe as R
     tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table_ec_vp.txt"))
-    u0, RT, nu = 0.1, 5.0, 0.01
-    errs = []
+    rec = _recipe_rows()
+    errs = {}
     for N in (16, 32):
-        d = dict(lattice=9, n=(N, N, 1), L=(1, 1, 1), rho0=1.0, RT=RT, tau=nu / RT,
-                 dt=2.5e-4, bc=(0,) * 6)
-        _, xc = O.mesh(d, 0)
-        X, Y = np.meshgrid(xc[1:-1], xc[1:-1], indexing="xy")
-        ua = np.stack([u0 * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y),
-                       u0 * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Y)])[:, None]
-        pa = 0.25 * u0 ** 2 * (np.cos(4 * np.pi * X) - np.cos(4 * np.pi * Y))[None]
-        F = 8 * np.pi ** 2 * nu * ua
-        f = O.init(d, rho=1.0 + pa / RT, u=ua, force=F)
-        f = run_to(d, f, 3.0, force=F)
-        _, u, p, _ = O.moments(d, f, force=F)
-        errs.append(np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum()))
-    order = np.log2(errs[0] / errs[1])
-    assert 1.8 < order < 2.3
-    for N, e in zip((16, 32), errs):
-        printed = tab[tab[:, 0] == N][0, 1]
-        assert printed < e < 8 * printed
+        eu, ep, amp, n = R.steady_errors(N, 1e-4)
+        errs[N] = (eu, ep)
+        printed_u, printed_p = tab[tab[:, 0] == N][0, 1:3]
+        assert eu / printed_u == pytest.approx(rec[N]["ru"], rel=0.2)
+        assert ep / printed_p == pytest.approx(rec[N]["rp"], rel=0.2)
+        assert amp > 1.0  # the steady velocity is larger than the analytic one
+    assert 1.8 < np.log2(errs[16][0] / errs[32][0]) < 2.2
+    assert 1.6 < np.log2(errs[16][1] / errs[32][1]) < 2.2
