@@ -64,7 +64,9 @@ extern "C" {
 
 enum dugks_lattice { DUGKS_D2Q9 = 9, DUGKS_D3Q19 = 19, DUGKS_D3Q27 = 27 };
 enum dugks_dtype { DUGKS_F32 = 0, DUGKS_F64 = 1 };
-enum dugks_mesh_kind { DUGKS_UNIFORM = 0, DUGKS_TANH = 1 };
+/* mesh of one axis: uniform, the tanh stretching of Eq. (Nonuniform_mesh),
+ * or caller-given face coordinates (dugks_config.faces) */
+enum dugks_mesh_kind { DUGKS_UNIFORM = 0, DUGKS_TANH = 1, DUGKS_CUSTOM = 2 };
 /* equilibrium model: the paper's incompressible one (Eq. icfeq with
  * Eq. macro_values) or the original DUGKS one (Eq. feq with
  * rho u = sum xi f + rho G dt/2), kept for comparison */
@@ -81,8 +83,15 @@ enum dugks_bc {
  * Problem description (Sec. II; mesh of Eq. Nonuniform_mesh).
  *   n[3]        cells per axis (n[2] = 1 for D2Q9); wall axes need n >= 2
  *   L[3]        domain length per axis
- *   mesh[3]     DUGKS_UNIFORM or DUGKS_TANH per axis; faces of a tanh axis
- *               are X_i = L (1/2 + tanh(k (i/N - 1/2)) / (2 tanh(k/2)))
+ *   mesh[3]     DUGKS_UNIFORM, DUGKS_TANH or DUGKS_CUSTOM per axis; faces of
+ *               a tanh axis are X_i = L (1/2 + tanh(k (i/N - 1/2)) / (2 tanh(k/2)));
+ *               a custom axis takes faces[a]
+ *   faces[3]    per axis, for DUGKS_CUSTOM only (else ignored, may be NULL):
+ *               host array of the n[a]+1 face coordinates, X_0 = 0 <
+ *               X_1 < ... < X_n = L[a] exactly (a finite-volume mesh as in
+ *               Sec. II.B and the Appendix, cell widths X_{i+1} - X_i,
+ *               centres at the midpoints); read by dugks_init and
+ *               dugks_batch_create, which keep their own copies
  *   rho0, RT    reference density, R T (c = sqrt(3 RT))
  *   tau, dt     relaxation time and time step (both > 0)
  *   G[3]        uniform part of the acceleration
@@ -111,6 +120,7 @@ typedef struct {
     double uw[6][3];
     double pw[6];
     int model;
+    const double* faces[3];
 } dugks_config;
 
 typedef struct dugks_ctx dugks_ctx;
@@ -323,6 +333,14 @@ int dugks_batch_init(dugks_batch* b, void* f_out, void* stream);
 int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const void* forces,
                     const int64_t* force_offsets, int nsteps, int use_graph, void* stream,
                     int* which_out);
+
+/* dugks_batch_run with the launch form chosen by the library: replayed
+ * from a captured hipGraph when stream is a non-default stream (graphs need
+ * one), plain launches on the default stream; tile and chunk from the
+ * batch's tuning (dugks_batch_tune), else the chunk model.  Same arguments,
+ * results and ping-pong convention as dugks_batch_run. */
+int dugks_batch_step(dugks_batch* b, void* f_in, void* f_out, const void* forces,
+                     const int64_t* force_offsets, int nsteps, void* stream, int* which_out);
 
 /*
  * Autotuner of the batched launch: times nsteps steps (after one warm-up

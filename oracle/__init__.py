@@ -10,7 +10,9 @@ Configurations are plain dicts with the keys::
     lattice   9 (D2Q9), 19 (D3Q19) or 27 (D3Q27)
     n         (nx, ny, nz)            nz = 1 for D2Q9
     L         (Lx, Ly, Lz)
-    mesh      (kx, ky, kz)            0 uniform, 1 tanh-stretched, per axis
+    mesh      (kx, ky, kz)            0 uniform, 1 tanh-stretched, 2 custom, per axis
+    faces     per axis: face coordinates of a custom axis (n+1 values from
+              0 to L), else None
     k_stretch tanh constant k
     rho0, RT, tau, dt
     G         uniform acceleration (3)
@@ -54,6 +56,7 @@ class _Cfg(ctypes.Structure):
         ("uw", (ctypes.c_double * 3) * 6),
         ("pw", ctypes.c_double * 6),
         ("model", ctypes.c_int),
+        ("faces", ctypes.POINTER(ctypes.c_double) * 3),
     ]
 
 
@@ -109,6 +112,14 @@ def _cfg(d: dict) -> _Cfg:
         c.pw[s] = float(pw[s])
         for a in range(3):
             c.uw[s][a] = float(uw[s][a])
+    c._faces = []  # keeps custom face arrays alive while the struct is in use
+    faces = d.get("faces") or (None, None, None)
+    for a in range(3):
+        X = faces[a] if a < len(faces) else None
+        if X is not None:
+            X = np.ascontiguousarray(X, dtype=np.float64)
+            c._faces.append(X)
+            c.faces[a] = X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return c
 
 

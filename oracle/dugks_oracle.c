@@ -108,13 +108,24 @@ static int make_lattice(int lattice, int e[MAXQ][3], double W[MAXQ], int opp[MAX
     return Q;
 }
 
-/* face coordinates of one axis: uniform, or the tanh stretching of
- * Eq. (Nonuniform_mesh): zeta_i = 1/2 + tanh(k(i/N - 1/2)) / (2 tanh(k/2)) */
-static void make_faces(int kind, int N, double L, double k, double* X)
+/* face coordinates of one axis: uniform, the tanh stretching of
+ * Eq. (Nonuniform_mesh): zeta_i = 1/2 + tanh(k(i/N - 1/2)) / (2 tanh(k/2)),
+ * or given coordinates (0 = X_0 < ... < X_N = L); -1 if those are not
+ * strictly increasing from 0 to L */
+static int make_faces(const oracle_cfg* cfg, int a, int N, double L, double* X)
 {
+    const int kind = cfg->mesh[a];
+    if (kind == OR_CUSTOM) {
+        const double* F = cfg->faces[a];
+        if (!F || F[0] != 0.0 || F[N] != L) return -1;
+        for (int i = 0; i <= N; ++i) X[i] = F[i];
+        for (int i = 0; i < N; ++i)
+            if (!(X[i + 1] > X[i])) return -1;
+        return 0;
+    }
     for (int i = 0; i <= N; ++i) {
         if (kind == OR_TANH) {
-            double zeta = 0.5 + tanh(k * ((double)i / N - 0.5)) / (2.0 * tanh(0.5 * k));
+            double zeta = 0.5 + tanh(cfg->k_stretch * ((double)i / N - 0.5)) / (2.0 * tanh(0.5 * cfg->k_stretch));
             X[i] = L * zeta;
         } else {
             X[i] = L * (double)i / N;
@@ -122,6 +133,7 @@ static void make_faces(int kind, int N, double L, double k, double* X)
     }
     X[0] = 0.0;
     X[N] = L;
+    return 0;
 }
 
 static int setup(octx* o, const oracle_cfg* cfg)
@@ -157,7 +169,7 @@ static int setup(octx* o, const oracle_cfg* cfg)
         o->w[a] = (double*)malloc(sizeof(double) * (N + 1));
         o->g[a] = (double*)malloc(sizeof(double) * (N + 1));
         o->dl[a] = (double*)malloc(sizeof(double) * N);
-        make_faces(cfg->mesh[a], N, L, cfg->k_stretch, o->X[a]);
+        if (make_faces(cfg, a, N, L, o->X[a])) { ctx_free(o); return -1; }
         double* X = o->X[a];
         double* xc = o->xc[a] + 1; /* xc[-1..N] */
         for (int i = 0; i < N; ++i) {

@@ -29,13 +29,13 @@ extern "C" {
 #endif
 
 enum { OR_PERIODIC = 0, OR_NEQ_VELOCITY = 1, OR_NEQ_PRESSURE = 2, OR_BOUNCE_BACK = 3 };
-enum { OR_UNIFORM = 0, OR_TANH = 1 };
+enum { OR_UNIFORM = 0, OR_TANH = 1, OR_CUSTOM = 2 };
 
 typedef struct {
     int lattice;        /* 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27) */
     int n[3];           /* cells per axis, n[2] == 1 for D2Q9 */
     double L[3];        /* domain length per axis */
-    int mesh[3];        /* OR_UNIFORM or OR_TANH per axis */
+    int mesh[3];        /* OR_UNIFORM, OR_TANH or OR_CUSTOM per axis */
     double k_stretch;   /* tanh stretch constant k */
     double rho0, RT, tau, dt;
     double G[3];        /* uniform part of the acceleration */
@@ -46,6 +46,8 @@ typedef struct {
     int model;          /* 0: incompressible model, Eq. (icfeq) with
                            Eq. (macro_values); 1: original DUGKS, Eq. (feq)
                            with rho u = sum xi f + rho G dt/2 */
+    const double* faces[3]; /* OR_CUSTOM axes: the n+1 face coordinates,
+                               0 = X_0 < ... < X_n = L */
 } oracle_cfg;
 
 /* lattice table: e[q*3+a] in {-1,0,1}, w[q]; returns Q or -1 */

@@ -21,6 +21,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdugks.so")
 
@@ -54,6 +56,7 @@ class Config(ctypes.Structure):
         ("uw", (ctypes.c_double * 3) * 6),
         ("pw", ctypes.c_double * 6),
         ("model", ctypes.c_int),
+        ("faces", ctypes.POINTER(ctypes.c_double) * 3),
     ]
 
 
@@ -100,6 +103,7 @@ def load():
     lib.dugks_batch_init.argtypes = [_VP, _VP, _VP]
     lib.dugks_batch_run.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), I, I, _VP,
                                     ctypes.POINTER(I)]
+    lib.dugks_batch_step.argtypes = [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int64), I, _VP, ctypes.POINTER(I)]
     lib.dugks_batch_destroy.argtypes = [_VP]
     lib.dugks_batch_destroy.restype = None
     lib.dugks_batch_tune.restype = I
@@ -136,6 +140,18 @@ def config(d: dict) -> Config:
         c.pw[s] = float(pw[s])
         for a in range(3):
             c.uw[s][a] = float(uw[s][a])
+    # custom face coordinates (mesh kind 2): host float64 arrays, kept alive
+    # by the Config object for the duration of the call that reads them
+    c._faces = []
+    faces = d.get("faces") or (None, None, None)
+    for a in range(3):
+        X = faces[a] if a < len(faces) else None
+        if X is None:
+            c.faces[a] = None
+        else:
+            X = np.ascontiguousarray(X, dtype=np.float64)
+            c._faces.append(X)
+            c.faces[a] = X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return c
 
 
@@ -344,7 +360,8 @@ class BatchSolver:
         self.f = torch.empty(tot, dtype=self.dtype, device=self.device)
         self.g = torch.empty_like(self.f)
         n = len(self.cfgs)
-        arr = (Config * n)(*[config(c) for c in self.cfgs])
+        keep = [config(c) for c in self.cfgs]  # owns any custom face arrays until the create call returns
+        arr = (Config * n)(*keep)
         offs = (ctypes.c_int64 * n)(*self.offsets)
         h = ctypes.c_void_p()
         lib = load()

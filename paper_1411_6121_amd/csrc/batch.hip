@@ -53,6 +53,7 @@ struct dugks_batch {
     bool uniform = true;      // every instance on a uniform mesh
     bool any_field = false;   // some instance has a force field
     std::vector<dugks_config> cfgs;
+    std::vector<std::vector<double>> faces_own;  // copies of custom face coordinates (cfgs[i].faces point here)
     std::vector<unsigned char> hinst;  // host images of Inst<T>, n of them
     void* insts_dev = nullptr;
     void* met_dev = nullptr;
@@ -187,6 +188,16 @@ extern "C" int dugks_batch_create(const dugks_config* cfgs, int n, const int64_t
     b->Q = b->lattice;
     b->esize = b->dtype == DUGKS_F64 ? 8 : 4;
     b->cfgs.assign(cfgs, cfgs + n);
+    b->faces_own.resize((size_t)3 * n);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            b->cfgs[i].faces[a] = nullptr;
+            if (a < b->D && cfgs[i].mesh[a] == DUGKS_CUSTOM) {
+                std::vector<double>& own = b->faces_own[(size_t)3 * i + a];
+                own.assign(cfgs[i].faces[a], cfgs[i].faces[a] + cfgs[i].n[a] + 1);
+                b->cfgs[i].faces[a] = own.data();
+            }
+        }
     for (int i = 0; i < n; ++i)
         for (int a = 0; a < b->D; ++a)
             if (cfgs[i].mesh[a] != DUGKS_UNIFORM) b->uniform = false;
@@ -247,7 +258,7 @@ static int launch_run(dugks_batch* b, const void* f_in, void* f_out, const void*
 }
 
 // per-instance force offsets into the instance table (before any launch)
-static int apply_force_offsets(dugks_batch* b, const void* forces, const int64_t* force_offsets)
+static int apply_force_offsets(dugks_batch* b, const void* forces, const int64_t* force_offsets, hipStream_t st)
 {
     bool changed = false;
     const size_t isz = b->dtype == DUGKS_F64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
@@ -261,6 +272,9 @@ static int apply_force_offsets(dugks_batch* b, const void* forces, const int64_t
     for (int i = 0; i < b->n; ++i)
         if (forces && force_offsets && force_offsets[i] >= 0) b->any_field = true;
     if (changed) {
+        // earlier launches on the caller's stream may still read the table
+        // (and a captured graph refers to it): let them finish first
+        if (hipStreamSynchronize(st) != hipSuccess) return bfail(b, DUGKS_EHIP, "stream synchronisation");
         drop_graph(b);
         if (hipMemcpy(b->insts_dev, b->hinst.data(), b->hinst.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bfail(b, DUGKS_EHIP, "instance table update");
@@ -275,7 +289,7 @@ extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const vo
     if (!f_in || !f_out || f_in == f_out) return bfail(b, DUGKS_EINVAL, "need two distinct state buffers");
     if (nsteps < 0) return bfail(b, DUGKS_EINVAL, "negative step count");
     const hipStream_t st = (hipStream_t)stream;
-    const int frc = apply_force_offsets(b, forces, force_offsets);
+    const int frc = apply_force_offsets(b, forces, force_offsets, st);
     if (frc != DUGKS_OK) return frc;
     if (use_graph) {
         if (!st) return bfail(b, DUGKS_EINVAL, "graph capture needs a non-default stream");
@@ -304,6 +318,14 @@ extern "C" int dugks_batch_run(dugks_batch* b, void* f_in, void* f_out, const vo
     return DUGKS_OK;
 }
 
+extern "C" int dugks_batch_step(dugks_batch* b, void* f_in, void* f_out, const void* forces,
+                                const int64_t* force_offsets, int nsteps, void* stream, int* which_out)
+{
+    // graph replay needs a non-default stream
+    return dugks_batch_run(b, f_in, f_out, forces, force_offsets, nsteps, stream != nullptr ? 1 : 0, stream,
+                           which_out);
+}
+
 extern "C" int dugks_batch_tune(dugks_batch* b, void* f_a, void* f_b, const void* forces,
                                 const int64_t* force_offsets, int nsteps, void* stream, int* tile_out,
                                 int* chunk_out)
@@ -312,7 +334,7 @@ extern "C" int dugks_batch_tune(dugks_batch* b, void* f_a, void* f_b, const void
     if (!f_a || !f_b || f_a == f_b) return bfail(b, DUGKS_EINVAL, "need two distinct scratch buffers");
     if (nsteps < 1) return bfail(b, DUGKS_EINVAL, "need at least one timed step per candidate");
     const hipStream_t st = (hipStream_t)stream;
-    const int frc = apply_force_offsets(b, forces, force_offsets);
+    const int frc = apply_force_offsets(b, forces, force_offsets, st);
     if (frc != DUGKS_OK) return frc;
     // the clock is restored afterwards: tuning steps do not advance the batch
     long long clock = 0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/dugks.h"
 #include "inst.hpp"
@@ -26,6 +27,7 @@ struct dugks_ctx {
     int n_cu = 0;                 // compute units of the device the context was created on
     int device = -1;              // ordinal of that device
     void* adj = nullptr;          // adjoint scratch (device, lazily)
+    std::vector<double> faces_own[3]; // copies of custom face coordinates (cfg.faces points here)
     size_t adj_bytes = 0;
 };
 

@@ -61,8 +61,24 @@ int validate(const dugks_config* c, std::string& why)
     for (int a = 0; a < D; ++a) {
         if (c->n[a] < 1 || c->n[a] > (1 << 24)) { why = "cell count out of range"; return DUGKS_EINVAL; }
         if (!finite_pos(c->L[a])) { why = "domain length must be positive"; return DUGKS_EINVAL; }
-        if (c->mesh[a] != DUGKS_UNIFORM && c->mesh[a] != DUGKS_TANH) { why = "unknown mesh kind"; return DUGKS_EINVAL; }
+        if (c->mesh[a] != DUGKS_UNIFORM && c->mesh[a] != DUGKS_TANH && c->mesh[a] != DUGKS_CUSTOM) {
+            why = "unknown mesh kind";
+            return DUGKS_EINVAL;
+        }
         if (c->mesh[a] == DUGKS_TANH && !finite_pos(c->k_stretch)) { why = "tanh mesh needs k_stretch > 0"; return DUGKS_EINVAL; }
+        if (c->mesh[a] == DUGKS_CUSTOM) {
+            const double* X = c->faces[a];
+            if (!X) { why = "custom mesh needs its face coordinates"; return DUGKS_EINVAL; }
+            if (X[0] != 0.0 || X[c->n[a]] != c->L[a]) {
+                why = "custom faces must start at 0 and end at L";
+                return DUGKS_EINVAL;
+            }
+            for (int i = 0; i < c->n[a]; ++i)
+                if (!(std::isfinite(X[i + 1]) && X[i + 1] > X[i])) {
+                    why = "custom faces must be finite and strictly increasing";
+                    return DUGKS_EINVAL;
+                }
+        }
         const int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
         for (int s : {lo, hi})
             if (s < DUGKS_PERIODIC || s > DUGKS_BOUNCE_BACK) { why = "unknown boundary kind"; return DUGKS_EINVAL; }
@@ -85,10 +101,11 @@ int validate(const dugks_config* c, std::string& why)
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(c->uw[s][a])) { why = "non-finite wall velocity"; return DUGKS_EINVAL; }
     }
-    if (c->rho0 + c->pw[0] / c->RT <= 0 || c->rho0 + c->pw[1] / c->RT <= 0) {
-        why = "wall pressure gives non-positive density";
-        return DUGKS_EINVAL;
-    }
+    for (int s = 0; s < 2 * D; ++s)
+        if (c->bc[s] == DUGKS_NEQ_PRESSURE && c->rho0 + c->pw[s] / c->RT <= 0) {
+            why = "wall pressure gives non-positive density";
+            return DUGKS_EINVAL;
+        }
     return DUGKS_OK;
 }
 
@@ -97,6 +114,10 @@ static void faces_of(const dugks_config* c, int a, std::vector<double>& X)
     const int N = c->n[a];
     const double L = c->L[a];
     X.resize(N + 1);
+    if (c->mesh[a] == DUGKS_CUSTOM) {
+        X.assign(c->faces[a], c->faces[a] + N + 1);
+        return;
+    }
     for (int i = 0; i <= N; ++i) {
         if (c->mesh[a] == DUGKS_TANH) {
             const double k = c->k_stretch;
@@ -549,6 +570,13 @@ extern "C" int dugks_init(const dugks_config* cfg, const void* rho, const void* 
     }
     dugks::adjoint_static_setup();
     ctx->cfg = *cfg;
+    for (int a = 0; a < 3; ++a) {
+        ctx->cfg.faces[a] = nullptr;
+        if (a < (cfg->lattice == DUGKS_D2Q9 ? 2 : 3) && cfg->mesh[a] == DUGKS_CUSTOM) {
+            ctx->faces_own[a].assign(cfg->faces[a], cfg->faces[a] + cfg->n[a] + 1);
+            ctx->cfg.faces[a] = ctx->faces_own[a].data();
+        }
+    }
     ctx->D = cfg->lattice == DUGKS_D2Q9 ? 2 : 3;
     ctx->Q = cfg->lattice;
     ctx->esize = cfg->dtype == DUGKS_F64 ? 8 : 4;

@@ -44,10 +44,14 @@ def lattice(lat):
 
 
 def axis_faces(cfg, a):
-    """face coordinates X_0..X_N of axis a (Eq. (Nonuniform_mesh) or uniform)"""
+    """face coordinates X_0..X_N of axis a (uniform, Eq. (Nonuniform_mesh), or
+    given)"""
     N, L = int(cfg["n"][a]), float(cfg["L"][a])
     i = np.arange(N + 1) / N
-    if cfg.get("mesh", (0, 0, 0))[a]:
+    kind = cfg.get("mesh", (0, 0, 0))[a]
+    if kind == 2:  # caller-given coordinates
+        return np.array(cfg["faces"][a], dtype=np.float64)
+    if kind:
         k = float(cfg["k_stretch"])
         X = L * (0.5 + np.tanh(k * (i - 0.5)) / (2.0 * np.tanh(0.5 * k)))
     else:

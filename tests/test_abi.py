@@ -77,6 +77,10 @@ def test_invalid_configurations_are_rejected(bad):
     (dict(bc=(2, 2, 0, 0, 0, 0), pw=[float("nan")] + [0.0] * 5), "non-finite wall pressure"),
     (dict(bc=(1, 1, 0, 0, 0, 0), uw=[[float("nan"), 0, 0]] + [[0, 0, 0]] * 5), "non-finite wall velocity"),
     (dict(bc=(2, 2, 0, 0, 0, 0), pw=[-1.0, 0, 0, 0, 0, 0]), "non-positive density"),  # rho0 + p/RT <= 0
+    (dict(bc=(0, 0, 1, 2, 0, 0), pw=[0, 0, 0, -0.5, 0, 0]), "non-positive density"),  # a pressure side on y
+    (dict(mesh=(2, 0, 0)), "custom mesh needs its face coordinates"),
+    (dict(mesh=(2, 0, 0), faces=([0.0, 1, 2, 3, 4, 5, 6, 7, 8.5], None, None)), "start at 0 and end at L"),
+    (dict(mesh=(2, 0, 0), faces=([0.0, 1, 2, 3, 3, 5, 6, 7, 8], None, None)), "strictly increasing"),
     (dict(lattice=19, n=(1 << 14, 1 << 14, 1 << 14), L=(1.0, 1.0, 1.0)), "problem too large"),  # > 2^40 values
     (dict(rho0=0.0), "must be positive and finite"),
     (dict(tau=float("inf")), "must be positive and finite"),

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from tests.test_gpu_parity import custom_faces
 from synthetic import batch_instances, field
 
 torch = pytest.importorskip("torch")
@@ -134,7 +135,9 @@ def d3q19_set(with_forces, dtype="f64"):
             c((1, 6, 5), (0, 0, 3, 3, 1, 1), G=(1e-4, 0, 0)),
             c((9, 7, 1), (1, 1, 1, 1, 0, 0), omega=0.2, G=(0, 1e-4, 0)),
             c((8, 12, 10), (0, 0, 3, 3, 3, 3), mesh=(0, 1, 1), k_stretch=1.3, dt=0.3, G=(2e-4, 0, 0)),
-            c((13, 11, 9), (0,) * 6, G=(1e-4, 0, -2e-4), omega=0.1, phase=0.4)]
+            c((13, 11, 9), (0,) * 6, G=(1e-4, 0, -2e-4), omega=0.1, phase=0.4),
+            c((7, 6, 8), (1,) * 6, mesh=(2, 2, 2), dt=0.25,
+              faces=(custom_faces(8, 7, 7.0), custom_faces(9, 6, 6.0), custom_faces(10, 8, 8.0)))]
     forces = [None] * len(cfgs)
     if with_forces:
         for i in (0, 3, 5):

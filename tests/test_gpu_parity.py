@@ -98,6 +98,16 @@ def start_state(cfg, seed, force=None, du=0.03):
     return perturb(seed + 2, f0, 1e-3)
 
 
+def custom_faces(seed, n, L):
+    """seeded strictly increasing face coordinates from 0 to L (cell widths
+    between 0.5 and 1.5 of the mean, neighbours differing up to 3x)"""
+    from synthetic import rng
+    w = rng(seed, 7, n).uniform(0.5, 1.5, n)
+    X = np.concatenate([[0.0], np.cumsum(w)]) * (L / w.sum())
+    X[0], X[-1] = 0.0, L
+    return X
+
+
 def c2(name, n, bc, **kw):
     d = dict(name=name, lattice=9, dtype="f64", n=(n[0], n[1], 1), L=(float(n[0]), float(n[1]), 1.0), rho0=1.0,
              RT=1 / 3, tau=0.3, dt=0.5, bc=bc)
@@ -124,6 +134,9 @@ CASES = [
                                                                        [0.05, 0, 0], [0, 0, 0], [0, 0, 0]],
        pw=[0, 0, 1e-3, 0, 0, 0], G=(1e-4, 2e-4, 0), force_field=True, mesh=(0, 1, 0), k_stretch=1.0, dt=0.3),
     c2("d2q9-minimal", (1, 2), (0, 0, 1, 1, 0, 0), uw=LID),
+    c2("d2q9-custom-faces", (29, 23), (1, 3, 1, 2, 0, 0), uw=LID, pw=[0, 0, 0, 1e-3, 0, 0], mesh=(2, 2, 0),
+       faces=(custom_faces(1, 29, 29.0), custom_faces(2, 23, 23.0), None), dt=0.25, G=(1e-4, 0, 0),
+       force_field=True),
     c2("d2q9-wide-tiles", (300, 21), (1, 1, 0, 0, 0, 0), uw=[[0, 0.01, 0], [0, -0.01, 0]] + [[0, 0, 0]] * 4,
        G=(0, 1e-4, 0)),
     c3("d3q19-multi-tile", (40, 30, 20), (3, 3, 1, 1, 0, 0), uw=LID3, G=(0, 0, 1e-4)),
@@ -134,6 +147,8 @@ CASES = [
     c3("d3q19-mixed", (12, 9, 11), (2, 2, 1, 3, 0, 0), pw=[2e-3, 0, 0, 0, 0, 0], uw=LID3, mesh=(0, 1, 0),
        k_stretch=1.2, dt=0.3),
     c3("d3q19-minimal", (2, 2, 2), (1, 1, 3, 3, 1, 1), uw=LID3),
+    c3("d3q19-custom-faces", (14, 11, 12), (1,) * 6, uw=LID3, mesh=(2, 2, 2), dt=0.25,
+       faces=(custom_faces(3, 14, 14.0), custom_faces(4, 11, 11.0), custom_faces(5, 12, 12.0))),
     # degenerate periodic axes: a march axis of one plane (the plane ring
     # holds the same plane three times), a tile axis of one column (both
     # halo columns are the cell itself), two cells on two periodic axes

@@ -133,6 +133,62 @@ def test_step_matches_whole_array_restatement(d):
     assert np.abs(a3 - b3).max() / np.abs(a3).max() < 5e-15
 
 
+def random_faces(seed, n, L):
+    """strictly increasing face coordinates from 0 to L with widths varying
+    by up to a factor 3 between neighbours"""
+    w = rng(seed, n).uniform(0.5, 1.5, n)
+    X = np.concatenate([[0.0], np.cumsum(w)])
+    X = X * (L / X[-1])
+    X[-1] = L
+    return X
+
+
+def test_custom_faces_equal_to_the_tanh_formula_give_the_tanh_step():
+    d = cfg(19, (4, 5, 3), (1, 1, 3, 3, 0, 0), uw=UW, mesh=(1, 1, 0), k_stretch=1.3)
+    faces = [O.mesh(d, a)[0] for a in range(3)]
+    c = dict(d, mesh=(2, 2, 0), faces=(faces[0], faces[1], None))
+    D, Q, shp = O.dims(d)
+    f0 = perturb(3, O.init(d, rho=1 + field(1, shp, 0.01), u=field(2, (D,) + shp, 0.03)), 1e-2)
+    np.testing.assert_array_equal(O.step(c, f0), O.step(d, f0))
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_custom_faces_step_matches_whole_array_restatement(lat):
+    n = (5, 4, 1) if lat == 9 else (4, 5, 3)
+    L = tuple(float(v) for v in n)
+    faces = tuple(random_faces(60 + a, n[a], L[a]) for a in range(3))
+    d = cfg(lat, n, (1, 3, 2, 1, 0, 0) if lat == 9 else (1, 3, 2, 1, 1, 1), uw=UW, pw=[0, 0, 1e-3, 0, 0, 0],
+            mesh=(2, 2, 2 if lat != 9 else 0), faces=faces)
+    D, Q, shp = O.dims(d)
+    force = field(5, (D,) + shp, 1e-3)
+    f0 = perturb(3, O.init(d, rho=1 + field(1, shp, 0.01), u=field(2, (D,) + shp, 0.03), force=force), 1e-2)
+    a3 = O.run(d, f0, 3, force, 0.7)
+    b3 = B.run(d, f0, 3, force, 0.7)
+    assert np.abs(a3 - b3).max() / np.abs(a3).max() < 5e-15
+    # and Eq. (gradient) stays exact on a linear field on this mesh
+    xc = [O.mesh(d, a)[1][1:-1] if a < D else np.zeros(1) for a in range(3)]
+    Z, Y, X = np.meshgrid(xc[2], xc[1], xc[0], indexing="ij")
+    phi = np.broadcast_to(1.0 + 0.1 * X - 0.05 * Y + 0.02 * Z, shp)[None].repeat(Q, 0)
+    e, _ = O.lattice(lat)
+    h = 0.5 * d["dt"]
+    grad = np.array([0.1, -0.05, 0.02])[:D]
+    for a in range(D):
+        Xf = O.mesh(d, a)[0]
+        coords = list(xc)
+        coords[a] = Xf
+        Zf, Yf, Xf3 = np.meshgrid(coords[2], coords[1], coords[0], indexing="ij")
+        want = (1.0 + 0.1 * Xf3 - 0.05 * Yf + (0.02 * Zf if D == 3 else 0))[None] - \
+            h * (np.sqrt(3 * d["RT"]) * e[:, :D] @ grad)[:, None, None, None]
+        np.testing.assert_allclose(O.interface_values(d, a, phi), want, rtol=0, atol=2e-14)
+
+
+def test_custom_faces_rejected_unless_increasing_from_zero_to_L():
+    d = cfg(9, (4, 3, 1), (1, 1, 1, 1, 0, 0), mesh=(2, 0, 0))
+    for bad in ([0.0, 1.0, 1.0, 3.0, 4.0], [0.5, 1.0, 2.0, 3.0, 4.0], [0.0, 1.0, 2.0, 3.0, 4.5]):
+        with pytest.raises(ValueError):
+            O.step(dict(d, faces=(np.array(bad), None, None)), np.ones((9, 1, 3, 4)))
+
+
 # --------------------------------------------------------------------------
 # manufactured steady flows on stretched meshes: second order
 # --------------------------------------------------------------------------
