@@ -159,7 +159,7 @@ def batch_cfg(spec, dtype):
                 tau=nu / RT, dt=0.5, bc=bc, uw=uw, G=(spec["force"], 0.0, 0.0))
 
 
-def bench_batched(dtype="f64", count=64, steps=100, warmup=5):
+def bench_batched(dtype="f64", count=64, steps=5000, warmup=5):
     """one batched launch per step (graph replay) vs one plain launch per
     instance per step; both give bitwise-identical states"""
     import torch
@@ -440,17 +440,21 @@ def run_cavity12000(n, t_end, sample_dt=0.02):
             "velocity_change_1000_steps": float(f"{dn / bn:.3g}")}
 
 
-def bench_cavity12000(t_end128=3000.0, t_end_coarse=1500.0):
+def bench_cavity12000(sizes=(128, 96, 80)):
+    """128^2 and 96^2 to t = 3000, 80^2 (steady early) to t = 1500"""
     out = {"workload": "D2Q9 cavity Re 12000, tanh mesh k = 2.5, bounce-back walls, f64, from rest",
            "paper": {"128": "periodic, main frequency 0.6144", "80, 96": "steady"}}
-    for n, te in ((128, t_end128), (96, t_end_coarse), (80, t_end_coarse)):
+    ends = {128: 3000.0, 96: 3000.0, 80: 1500.0}
+    for n in sizes:
+        te = ends.get(n, 3000.0)
         out[str(n)] = run_cavity12000(n, te)
         print(f"[re12000 {n}^2] {json.dumps(out[str(n)])}", file=sys.stderr, flush=True)
     return out
 
 
-def workload_name(n, mesh, re, dtype):
-    return f"D3Q19 {n}^3 lid-driven cavity, {mesh}, Re {re:g}, NEQ walls, {dtype}"
+def workload_name(n, mesh, re, dtype, lattice=19):
+    dims = f"{n}^2" if lattice == 9 else f"{n}^3"
+    return f"D{2 if lattice == 9 else 3}Q{lattice} {dims} lid-driven cavity, {mesh}, Re {re:g}, NEQ walls, {dtype}"
 
 
 def main():
@@ -462,6 +466,8 @@ def main():
     ap.add_argument("--mesh", default="uniform", choices=["uniform", "tanh"])
     ap.add_argument("--re", type=float, default=100.0)
     ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--lattice", type=int, default=19, choices=[9, 19, 27],
+                    help="velocity set of the timed cavity (the headline is D3Q19)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 / batched / adjoint figures")
     ap.add_argument("--copy-probe", action="store_true",
@@ -470,11 +476,13 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="print only the adjoint figures (periodic and walled D2Q9 256^2) as one JSON line")
     ap.add_argument("--cavity-re12000", action="store_true",
-                    help="run the Re = 12000 2-D cavity (128^2 to t = 3000, 96^2 and 80^2 to t = 1500; "
-                         "about five minutes) and print its JSON line instead of the benchmark")
+                    help="run the Re = 12000 2-D cavity (128^2 and 96^2 to t = 3000, 80^2 to t = 1500; "
+                         "about six minutes) and print its JSON line instead of the benchmark")
+    ap.add_argument("--re12000-sizes", type=int, nargs="+", default=[128, 96, 80],
+                    help="meshes of the Re = 12000 run")
     args = ap.parse_args()
 
-    workload = workload_name(args.n, args.mesh, args.re, args.dtype)
+    workload = workload_name(args.n, args.mesh, args.re, args.dtype, args.lattice)
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, workload)
         return
@@ -490,12 +498,12 @@ def main():
 
     torch.cuda.init()
     if args.cavity_re12000:
-        print(json.dumps(bench_cavity12000()))
+        print(json.dumps(bench_cavity12000(tuple(args.re12000_sizes))))
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": bench_adjoint(), "adjoint_walls": bench_adjoint(walls=True)}))
         return
-    cfg = cavity_cfg(args.n, args.dtype, args.mesh, args.re)
+    cfg = cavity_cfg(args.n, args.dtype, args.mesh, args.re, lattice=args.lattice)
     Q, D, shp = M.shape_of(cfg)
     cells = int(shp[0] * shp[1] * shp[2])
     esize = 8 if args.dtype == "f64" else 4
@@ -544,7 +552,7 @@ def main():
         "wall_s_timed": round(wall, 3),
         "mass_total": tot[0],
     }
-    if not args.no_extras:
+    if not args.no_extras and args.lattice == 19:
         also = {}
         if args.dtype == "f64":
             c32 = cavity_cfg(args.n, "f32", args.mesh, args.re)
@@ -580,7 +588,23 @@ def main():
         b27 = 2.0 * 27 * esize * cells
         also["d3q27"] = {"ms_per_step": round(ms27, 5), "mlups": round(cells / ms27 / 1e3, 2),
                          "hbm_frac": round(b27 / (ms27 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # configs[2] on the stretched mesh (tanh k = 1.5, Re 1000), both precisions
+        for dt_name in ("f64", "f32"):
+            ct = cavity_cfg(args.n, dt_name, "tanh", 1000.0)
+            f = torch.empty((Q,) + shp, dtype=M.torch_dtype(ct), device="cuda")
+            g = torch.empty_like(f)
+            ctx = M.dugks_init(ct, f)
+            kvt = M.dugks_kernel_variant(ctx)
+            mst, _ = time_steps(ctx, ct, f, g, max(args.steps // 2, 10), max(args.warmup // 2, 2))
+            M.dugks_destroy(ctx)
+            del f, g
+            bt = 2.0 * Q * (8 if dt_name == "f64" else 4) * cells
+            also[f"tanh_re1000_{dt_name}"] = {
+                "ms_per_step": round(mst, 5), "mlups": round(cells / mst / 1e3, 2),
+                "hbm_frac": round(bt / (mst * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "kernel": {0: "general", 1: "fused-twice", 2: "fused", 3: "fused-split"}.get(kvt, str(kvt))}
         also["batched"] = bench_batched()
+        also["batched_f32"] = bench_batched("f32")
         also["adjoint"] = bench_adjoint()
         also["adjoint_walls"] = bench_adjoint(walls=True)
         res["also"] = also

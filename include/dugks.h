@@ -345,7 +345,10 @@ int dugks_batch_step(dugks_batch* b, void* f_in, void* f_out, const void* forces
 /*
  * Autotuner of the batched launch: times nsteps steps (after one warm-up
  * step) for every tile shape of the lattice (D3Q19: 18 x 14 columns; D2Q9:
- * rows of 128, 64 or 256 columns) and march chunk 4, 8, 16, 32, 64 planes,
+ * rows of 128, 64 or 256 columns) and every chunk policy: each instance's
+ * own march chunk from the chunk model (the device's resident workgroups
+ * shared among the instances in proportion to their cells; chunk 0, also
+ * the batch's default), or one chunk of 4, 8, 16, 32 or 64 planes for all,
  * and keeps the fastest for later dugks_batch_run calls.  Results do not
  * depend on the choice (every interface is evaluated by the same code in
  * any tiling), so tuning never changes a state.
@@ -354,6 +357,7 @@ int dugks_batch_step(dugks_batch* b, void* f_in, void* f_out, const void* forces
  *              one); both are overwritten
  *   forces, force_offsets  as in dugks_batch_run (the tuned workload)
  *   tile_out, chunk_out    nullable: the chosen tile variant and chunk
+ *                          policy (0 = per-instance chunks)
  * Synchronises the stream; the batch clock is left unchanged.  Drops any
  * captured graph.  DUGKS_EINVAL for bad arguments or nsteps < 1.
  */

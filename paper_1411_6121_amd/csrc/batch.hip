@@ -11,8 +11,10 @@
 
 #include "ctx.hpp"
 #include "kernels_general.hpp"
+#include "march.hpp"
 
 namespace dugks {
+long long batch_resident_slots(int lattice, int dtype, bool uniform, int variant, int n_cu);
 hipError_t batch_step_launch(int lattice, int dtype, bool uniform, int variant, const void* insts,
                              const long long* bstart, const BatchGeom* geom, int n, long long nblocks, const void* fin,
                              const void* forces, void* fout, const long long* step0, int step, hipStream_t st);
@@ -95,13 +97,26 @@ size_t metric_len(const dugks_config* c);
 }  // namespace dugks
 
 // Workgroup geometry of every instance for tile-shape variant `tile` and
-// march chunk `chunk` (0: 16 planes in 3-D, 8 in 2-D): tile counts, chunk and
-// the workgroup prefix sum; uploaded synchronously (never inside a capture).
+// march chunk `chunk`: tile counts, chunk and the workgroup prefix sum;
+// uploaded synchronously (never inside a capture).  chunk > 0: the same chunk
+// for every instance; chunk = 0: a chunk per instance from the chunk model
+// (auto_chunk) with the device's resident workgroups shared among the
+// instances in proportion to their cells, so that large instances march
+// long chunks (fewer recomputed halo planes) and small ones short chunks
+// (more workgroups at once).
 static int set_geometry(dugks_batch* b, int tile, int chunk)
 {
     const int n = b->n, D = b->D, M = D - 1;
     int bx, by;
     fused_tile_shape(b->lattice, tile, &bx, &by);
+    long long slots = 0;
+    if (chunk == 0) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 0;
+        slots = batch_resident_slots(b->lattice, b->dtype, b->uniform, tile, ncu);
+    }
     std::vector<long long> bstart(n + 1, 0);
     std::vector<BatchGeom> geom(n);
     for (int i = 0; i < n; ++i) {
@@ -109,7 +124,14 @@ static int set_geometry(dugks_batch* b, int tile, int chunk)
         BatchGeom g;
         g.tiles0 = (nn[0] + bx - 3) / (bx - 2);
         g.tiles1 = D == 3 ? (nn[1] + by - 3) / (by - 2) : 1;
-        g.chunk = std::min(chunk > 0 ? chunk : (D == 3 ? 16 : 8), nn[M]);
+        if (chunk > 0) {
+            g.chunk = std::min(chunk, nn[M]);
+        } else {
+            long long cells = 1;
+            for (int a = 0; a < D; ++a) cells *= nn[a];
+            const long long share = std::max(1LL, (long long)((double)slots * (double)cells / (double)b->ncells));
+            g.chunk = auto_chunk((long long)g.tiles0 * g.tiles1, nn[M], share);
+        }
         g.pad = 0;
         const int chunks = (nn[M] + g.chunk - 1) / g.chunk;
         geom[i] = g;
@@ -350,7 +372,8 @@ extern "C" int dugks_batch_tune(dugks_batch* b, void* f_a, void* f_b, const void
     }
     float best = -1.0f;
     int best_tile = 0, best_chunk = 0, rc = DUGKS_OK;
-    static const int chunks[] = {4, 8, 16, 32, 64};
+    // 0: a chunk per instance from the chunk model; else one chunk for all
+    static const int chunks[] = {0, 4, 8, 16, 32, 64};
     for (int tile = 0; tile < fused_tile_variants(b->lattice) && rc == DUGKS_OK; ++tile) {
         for (int chunk : chunks) {
             if (chunk > 2 * maxm) continue;

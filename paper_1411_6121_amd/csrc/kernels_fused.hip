@@ -746,6 +746,34 @@ hipError_t split_batch_launch(int lattice, int dtype, int variant, const void* i
                               const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
                               void* fout, const long long* step0, int step, hipStream_t st);
 
+long long split_batch_slots(int lattice, int dtype, int variant, int n_cu);
+
+template <class LAT, typename T, int BX, int BY, int MINW>
+static long long fused2_batch_slots_t(int n_cu)
+{
+    constexpr bool PF = prefetch_planes<LAT, T>();
+    return resident_slots(k_fused2_batch<LAT, T, BX, BY, MINW, PF, false>, BX * BY, fused2_lds<LAT, T, BX, BY>(), n_cu);
+}
+
+// workgroups of the batched step kernel (the one batch_step_launch takes)
+// resident on the device at once
+long long batch_resident_slots(int lattice, int dtype, bool uniform, int variant, int n_cu)
+{
+    if (default_step_kernel(lattice, dtype, uniform, false) == 3) return split_batch_slots(lattice, dtype, variant, n_cu);
+    if (lattice == DUGKS_D2Q9) {
+        if (dtype == DUGKS_F64) {
+            if (variant == 1) return fused2_batch_slots_t<D2Q9, double, 64, 1, 2>(n_cu);
+            if (variant == 2) return fused2_batch_slots_t<D2Q9, double, 256, 1, 2>(n_cu);
+            return fused2_batch_slots_t<D2Q9, double, 128, 1, 2>(n_cu);
+        }
+        if (variant == 1) return fused2_batch_slots_t<D2Q9, float, 64, 1, 2>(n_cu);
+        if (variant == 2) return fused2_batch_slots_t<D2Q9, float, 256, 1, 2>(n_cu);
+        return fused2_batch_slots_t<D2Q9, float, 128, 1, 2>(n_cu);
+    }
+    return dtype == DUGKS_F64 ? fused2_batch_slots_t<D3Q19, double, 18, 14, 1>(n_cu)
+                              : fused2_batch_slots_t<D3Q19, float, 18, 14, 2>(n_cu);
+}
+
 // one batched step on the default step kernel of the lattice and precision
 // (so that batched and single-instance runs give identical states)
 hipError_t batch_step_launch(int lattice, int dtype, bool uniform, int variant, const void* insts,

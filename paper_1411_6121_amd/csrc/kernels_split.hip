@@ -961,6 +961,30 @@ static hipError_t split_batch_launch_t(const void* insts, const long long* bstar
                                                                   step0, step, st);
 }
 
+template <class LAT, typename T, int BX, int BY, int MINW, bool PF>
+static long long split_batch_slots_t(int n_cu)
+{
+    return resident_slots(k_split_batch<LAT, T, BX, BY, MINW, PF, false>, split_threads<BX, BY>(),
+                          split_lds<LAT, T, BX, BY>(), n_cu);
+}
+
+// workgroups of the batched two-lane kernel resident on the device at once
+long long split_batch_slots(int lattice, int dtype, int variant, int n_cu)
+{
+    if (lattice == DUGKS_D2Q9) {
+        if (dtype == DUGKS_F64) {
+            if (variant == 1) return split_batch_slots_t<D2Q9, double, 64, 1, 2, false>(n_cu);
+            if (variant == 2) return split_batch_slots_t<D2Q9, double, 256, 1, 2, false>(n_cu);
+            return split_batch_slots_t<D2Q9, double, 128, 1, 2, false>(n_cu);
+        }
+        if (variant == 1) return split_batch_slots_t<D2Q9, float, 64, 1, 2, false>(n_cu);
+        if (variant == 2) return split_batch_slots_t<D2Q9, float, 256, 1, 2, false>(n_cu);
+        return split_batch_slots_t<D2Q9, float, 128, 1, 2, false>(n_cu);
+    }
+    return dtype == DUGKS_F64 ? split_batch_slots_t<D3Q19, double, 18, 14, 1, false>(n_cu)
+                              : split_batch_slots_t<D3Q19, float, 18, 14, 2, false>(n_cu);
+}
+
 hipError_t split_batch_launch(int lattice, int dtype, int variant, const void* insts, const long long* bstart,
                               const BatchGeom* geom, int n, long long nblocks, const void* fin, const void* forces,
                               void* fout, const long long* step0, int step, hipStream_t st)
