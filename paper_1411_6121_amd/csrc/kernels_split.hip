@@ -314,7 +314,10 @@ __device__ __forceinline__ void face_force_ring(const Inst<T>& P, const GV& gv, 
 // The interface of axis A with index f between the cells at offsets off and
 // off+1: steps 3-7 for the lane's velocities; out[half_cross_slot] receives
 // f (step 7) of the lane's velocities crossing the face.
-template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false, class GV>
+// NW: the caller knows that the face is no wall face (the wall code is
+// compiled out)
+template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false, bool NW = false,
+          class GV>
 __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const GV& gv,
                                           const int* ci, int off, int f, T gth, const CellMetric<T>& mx,
                                           const CellMetric<T>& my, const CellMetric<T>& mz, T sg, int sgi, T* out)
@@ -322,8 +325,8 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
     constexpr int K = LAT::REST;
     const AxisMetric<T>& m = P.m[A];
     const int n = P.n[A];
-    const bool wall_lo = !P.per[A] && f == 0;
-    const bool wall_hi = !P.per[A] && f == n;
+    const bool wall_lo = !NW && !P.per[A] && f == 0;
+    const bool wall_hi = !NW && !P.per[A] && f == n;
     NeqHalf<LAT, T> info;
     asm volatile("" ::: "memory");
     T fb[K], fr, G[3];
@@ -386,8 +389,13 @@ constexpr bool own_regs()
     return LAT::Q == 9 || (LAT::Q == 19 && UNI && !FF);
 }
 
+// NW: the workgroup's tile and chunk touch no wall (no wall faces, ghost
+// columns or ghost planes); that code is then compiled out of the body that
+// most workgroups of a large mesh run.  Used for D3Q19 launches of instances
+// without acceleration (elsewhere the second body costs spilled registers:
+// FP32 with acceleration, D3Q27)
 template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN, bool NOG = false, bool ORIG = false,
-          bool LPF = false>
+          bool LPF = false, bool NW = false>
 __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
                                            T* __restrict__ fout, T gt, T gth, int chunk, int tiles0, int tile,
                                            int ck, T* lds)
@@ -448,7 +456,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     const bool yface = (D == 3) && (cell_col || ghost_col) && col_ok && ty <= BY - 2 && g[1] >= -1 &&
                        g[1] <= P.n[1] - 1;
 
-    const bool any_ghost = __syncthreads_or(ghost_col) != 0;
+    const bool any_ghost = NW ? false : __syncthreads_or(ghost_col) != 0;
     const bool gr_on = (D == 2) && force != nullptr;
     auto gslot = [&](int p, int d) { return (ring(p) * D + d) * SQ + ty * BX + tx; };
     const int nM = P.n[M];
@@ -619,10 +627,10 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         return RingForce<T, BX, BY>{gr_on ? gring : nullptr, ring(z) * D * SQ + ty * BX + tx,
                                     (ring(z + 1) - ring(z)) * D * SQ, (ring(z - 1) - ring(z)) * D * SQ};
     };
-    auto computed = [&](int p) { return perM || p < nM; };
+    auto computed = [&](int p) { return NW || perM || p < nM; };
 
     int hi;
-    if (!perM && p0 == 0) {
+    if (!NW && !perM && p0 == 0) {
         load_plane(0);
         compute_plane(0);
         load_plane(1);
@@ -647,8 +655,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         ci[2] = (D == 3) ? p0 : 0;
         const CellMetric<T> cmm = load_metric(P, M, p0);
         const auto ph = phi_view(p0);
-        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(p0), ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
-        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(p0), ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
+        if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG, NW>(P, ph, force, gview(p0), ci, -1, p0, gth, cmx, cmy, cmm, sg, sgi, zlo);
+        else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG, NW>(P, ph, force, gview(p0), ci, -1, p0, gth, cmx, cmm, cmm, sg, sgi, zlo);
     }
     for (int z = p0; z < p1; ++z) {
         if (hi < z + 1) {
@@ -695,22 +703,22 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         T zhi[NM > 0 ? NM : 1];
         if (xface) {
             T v[NX];
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
 #pragma unroll
             for (int kc = 0; kc < NX; ++kc) fxb[((h * NX + kc) * BY + ty) * BX + tx] = v[kc];
         }
         if constexpr (D == 3) {
             if (yface) {
                 T v[NY];
-                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+                face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 1, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, g[1] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
 #pragma unroll
                 for (int kc = 0; kc < NY; ++kc) fyb[((h * NY + kc) * BY + ty) * BX + tx] = v[kc];
             }
         }
         if (upd_col) {
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
-            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG>(P, ph, force, gview(z), ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, z + 1, gth, cmx, cmy, cmm, sg, sgi, zhi);
+            else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, M, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, z + 1, gth, cmx, cmm, cmm, sg, sgi, zhi);
         }
         if (LP && z + 2 <= p1 && computed(z + 2) && pn_plane != z + 2) prefetch(z + 2);
         __syncthreads();
@@ -782,6 +790,22 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     }
 }
 
+// Does the workgroup of tile `tile` and march chunk `ck` (3-D) stay clear of
+// every wall?  Along a wall-bounded tile axis its columns (halo included) must
+// all be cells, and along a wall-bounded march axis its planes p0 - 1 ..
+// p1 must all be cells (no wall face, no ghost column or plane).
+template <typename T>
+__device__ __forceinline__ bool split_no_wall(const Inst<T>& P, int BX, int BY, int tiles0, int tile, int ck, int chunk)
+{
+    const int b0 = tile % tiles0, b1 = tile / tiles0;
+    const int x0 = b0 * (BX - 2) - 1, y0 = b1 * (BY - 2) - 1;
+    if (!P.per[0] && (x0 < 0 || x0 + BX - 1 > P.n[0] - 1)) return false;
+    if (!P.per[1] && (y0 < 0 || y0 + BY - 1 > P.n[1] - 1)) return false;
+    const int p0 = ck * chunk, p1 = min(p0 + chunk, P.n[2]);
+    if (!P.per[2] && (p0 < 1 || p1 > P.n[2] - 1)) return false;
+    return true;
+}
+
 // FF: the launch carries a force field (without one the kernel is compiled
 // with a null field and no field code)
 template <class LAT, typename T, int BX, int BY, int MINW, bool PF, bool FF, bool UNI, bool NOG, bool ORIG = false>
@@ -795,10 +819,17 @@ __global__ DUGKS_KERNEL_BOUNDS((split_threads<BX, BY>()), MINW, (max_waves_per_e
     const Inst<T>& P = *Pp;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * P.dtd);
     const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
-    split_body<LAT, T, BX, BY, PF, UNI, own_regs<LAT, T, UNI, FF>(), NOG, ORIG, !FF>(P, fin, FF ? force : nullptr, fout, gt, gth,
-                                                                         chunk,
-                                                                    tiles0, b % tiles, b / tiles,
-                                   reinterpret_cast<T*>(smem_raw));
+    const int tile = b % tiles, ck = b / tiles;
+    constexpr bool OWN = own_regs<LAT, T, UNI, FF>();
+    if constexpr (LAT::Q == 19 && NOG) {
+        if (split_no_wall(P, BX, BY, tiles0, tile, ck, chunk)) {
+            split_body<LAT, T, BX, BY, PF, UNI, OWN, NOG, ORIG, !FF, true>(
+                P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0, tile, ck, reinterpret_cast<T*>(smem_raw));
+            return;
+        }
+    }
+    split_body<LAT, T, BX, BY, PF, UNI, OWN, NOG, ORIG, !FF>(P, fin, FF ? force : nullptr, fout, gt, gth, chunk, tiles0,
+                                                             tile, ck, reinterpret_cast<T*>(smem_raw));
 }
 
 // batched form (see k_fused2_batch): workgroup b in XCD order belongs to the
