@@ -227,3 +227,23 @@ def test_large_periodic_mesh_64bit_offsets(G):
 def c3_periodic(p, G):
     return dict(lattice=19, dtype="f64", n=(p, p, p), L=(float(p),) * 3, rho0=1.0, RT=1 / 3, tau=0.3, dt=0.5,
                 bc=(0,) * 6, G=G)
+
+
+@pytest.mark.parametrize("lat,mesh,re,nsteps", [(19, "uniform", 100.0, 400), (19, "tanh", 1000.0, 400),
+                                                (27, "uniform", 100.0, 100)])
+def test_cavity_128_spanwise_mirror_symmetry(lat, mesh, re, nsteps):
+    # a property that holds at any size: the cavity from rest keeps the
+    # z -> L - z mirror symmetry (velocity (ex, ey, ez) -> (ex, ey, -ez)) to
+    # FP64 rounding over the GPU's own run
+    cfg = bench.cavity_cfg(128, "f64", mesh, re, lattice=lat)
+    oc = {k: v for k, v in cfg.items() if k != "dtype"}
+    say(f"[full size] D{3}Q{lat} 128^3 cavity {mesh} Re {re:g} f64: mirror symmetry after {nsteps} steps")
+    f = gpu_steps(cfg, O.init(oc), nsteps)
+    e, _ = O.lattice(lat)
+    idx = {tuple(v): k for k, v in enumerate(e)}
+    kmap = [idx[(v[0], v[1], -v[2])] for v in e]
+    err = np.abs(f - f[kmap][:, ::-1]).max() / np.abs(f).max()
+    uz = O.moments(oc, f)[1][2]
+    say(f"    mirror error {err:.2e}, max |u_z| {np.abs(uz).max():.2e}")
+    assert np.abs(uz).max() > 1e-6
+    assert err < 1e-12
