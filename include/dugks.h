@@ -104,6 +104,13 @@ enum dugks_bc {
  *               incompressible model would take it and no force field is
  *               given, else the general kernels; no batched form, no
  *               adjoint: DUGKS_EUNSUPPORTED there)
+ *   pw_osc[6]   oscillating part of the wall pressures: a pressure side
+ *               holds p_w(t) = pw[s] + pw_osc[s] g(t), with g the time
+ *               factor above taken at the interface time t_n + dt/2 of
+ *               the step (the pressure-driven flow of Sec. III.C, whose
+ *               inlet pressure follows Eq. Wom_AS_Pressure); zero for a
+ *               constant pressure.  rho0 + (pw - |pw_osc|) / RT must stay
+ *               positive.
  * D3Q27 has no batched form and no adjoint (DUGKS_EUNSUPPORTED).
  */
 typedef struct {
@@ -121,6 +128,7 @@ typedef struct {
     double pw[6];
     int model;
     const double* faces[3];
+    double pw_osc[6];
 } dugks_config;
 
 typedef struct dugks_ctx dugks_ctx;

@@ -19,7 +19,8 @@ Configurations are plain dicts with the keys::
     omega, phase                      g(t) = cos(omega t + phase)
     bc        6 side codes (-x,+x,-y,+y,-z,+z): 0 periodic, 1 NEQ velocity,
               2 NEQ pressure, 3 bounce-back
-    uw        6 x 3 wall velocities, pw  6 wall pressures
+    uw        6 x 3 wall velocities, pw  6 wall pressures, pw_osc  6
+              oscillating parts of the wall pressures (pw + pw_osc g(t))
     model     0 incompressible (default), 1 original DUGKS equilibrium
 
 Arrays: distributions ``f[q, z, y, x]``, vector fields ``v[d, z, y, x]``,
@@ -57,6 +58,7 @@ class _Cfg(ctypes.Structure):
         ("pw", ctypes.c_double * 6),
         ("model", ctypes.c_int),
         ("faces", ctypes.POINTER(ctypes.c_double) * 3),
+        ("pw_osc", ctypes.c_double * 6),
     ]
 
 
@@ -107,9 +109,11 @@ def _cfg(d: dict) -> _Cfg:
     c.model = int(d.get("model", 0))
     uw = d.get("uw", [[0.0] * 3] * 6)
     pw = d.get("pw", [0.0] * 6)
+    pwo = d.get("pw_osc", [0.0] * 6)
     for s in range(6):
         c.bc[s] = int(d["bc"][s])
         c.pw[s] = float(pw[s])
+        c.pw_osc[s] = float(pwo[s])
         for a in range(3):
             c.uw[s][a] = float(uw[s][a])
     c._faces = []  # keeps custom face arrays alive while the struct is in use

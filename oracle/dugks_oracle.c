@@ -582,15 +582,26 @@ static void interface_fbar(const octx* o, const double* phi, int a, const int* c
     }
 }
 
+/* Density of the pressure condition on side s, from p = (rho - rho0) RT:
+ * rho0 + p_w(t)/RT, where the wall pressure may follow the time factor g,
+ * p_w(t) = pw + pw_osc g(t) (the oscillating inlet pressure of the
+ * pressure-driven flow of Sec. III.C, Eq. (Wom_AS_Pressure)); g is taken at
+ * the interface time t_n + h. */
+static double pressure_wall_density(const oracle_cfg* cfg, int s, double g)
+{
+    return cfg->rho0 + (cfg->pw[s] + cfg->pw_osc[s] * g) / cfg->RT;
+}
+
 /* Wall interface of side s: the velocities entering the domain (xi.n < 0,
  * n the outward normal) are replaced by bounce-back, Eq. (BB) with
  * rho_w = rho0, or by non-equilibrium extrapolation, Eq. (NEQ), whose
  * non-equilibrium part is taken at x_c, the opposite interface of the same
  * wall cell (fo: f-bar there, rc/uc its moments).  Velocity condition:
- * (rho_alpha, u_alpha) = (rc, u_w); pressure condition: (rho0 + p_w/RT, uc).
+ * (rho_alpha, u_alpha) = (rc, u_w); pressure condition: (rho0 + p_w/RT, uc)
+ * with p_w at the interface time (time factor g).
  * The rules act on f-bar before its moments are taken. */
 static void wall_condition(const octx* o, const oracle_cfg* cfg, int s, double* fw, const double* fo, double rc,
-                           const double* uc)
+                           const double* uc, double g)
 {
     const int D = o->D, Q = o->Q, a = s / 2;
     const int out = (s % 2) ? 1 : -1; /* outward normal along a */
@@ -611,7 +622,7 @@ static void wall_condition(const octx* o, const oracle_cfg* cfg, int s, double* 
         ra = rc;
         for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
     } else {
-        ra = rho0 + cfg->pw[s] / RT;
+        ra = pressure_wall_density(cfg, s, g);
         for (int b = 0; b < D; ++b) ua[b] = uc[b];
     }
     for (int q = 0; q < Q; ++q) {
@@ -644,7 +655,7 @@ static void interface_flux(const octx* o, const oracle_cfg* cfg, const double* p
         interface_fbar(o, phi, a, co, h, fo);
         accel_face(o, cfg, Gext, a, co, gth, Go);
         point_macro(o, cfg, fo, Go, h / 2.0, &rc, uc);
-        wall_condition(o, cfg, 2 * a + (c[a] == N), fb, fo, rc, uc);
+        wall_condition(o, cfg, 2 * a + (c[a] == N), fb, fo, rc, uc, gth);
     }
     accel_face(o, cfg, Gext, a, c, gth, G);
     point_macro(o, cfg, fb, G, h / 2.0, &rho, u);
@@ -1106,7 +1117,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                             ra = rc;
                             for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
                         } else {
-                            ra = rho0 + cfg->pw[s] / RT;
+                            ra = pressure_wall_density(cfg, s, gth);
                             for (int b = 0; b < D; ++b) ua[b] = uc[b];
                         }
                         for (int q = 0; q < Q; ++q) {
@@ -1218,7 +1229,7 @@ int oracle_step_adjoint(const oracle_cfg* cfg, const double* fin, const double* 
                             ra = rc;
                             for (int b = 0; b < D; ++b) ua[b] = cfg->uw[s][b];
                         } else {
-                            ra = rho0 + cfg->pw[s] / RT;
+                            ra = pressure_wall_density(cfg, s, gth);
                             for (int b = 0; b < D; ++b) ua[b] = uc[b];
                         }
                         double rcb = 0.0, ucb[3] = {0, 0, 0};

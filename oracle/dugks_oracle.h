@@ -48,6 +48,8 @@ typedef struct {
                            with rho u = sum xi f + rho G dt/2 */
     const double* faces[3]; /* OR_CUSTOM axes: the n+1 face coordinates,
                                0 = X_0 < ... < X_n = L */
+    double pw_osc[6];   /* oscillating part of the wall pressure: the
+                           pressure side holds pw + pw_osc g(t) */
 } oracle_cfg;
 
 /* lattice table: e[q*3+a] in {-1,0,1}, w[q]; returns Q or -1 */

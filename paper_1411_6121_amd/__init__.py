@@ -10,7 +10,8 @@ Configurations are plain dicts (keys as in ``dugks_config``)::
 
     lattice 9|19|27, dtype "f32"|"f64", n (3), L (3), mesh (3), k_stretch,
     rho0, RT, tau, dt, G (3), omega, phase, bc (6), uw (6x3), pw (6),
-    model (0 incompressible, 1 original DUGKS equilibrium)
+    model (0 incompressible, 1 original DUGKS equilibrium), faces (3 host
+    arrays, custom meshes), pw_osc (6: oscillating part of the wall pressures)
 
 Tensors: state ``[Q, nz, ny, nx]``, vector fields ``[D, nz, ny, nx]``,
 scalars ``[nz, ny, nx]``, all contiguous on the CUDA (HIP) device, in the
@@ -57,6 +58,7 @@ class Config(ctypes.Structure):
         ("pw", ctypes.c_double * 6),
         ("model", ctypes.c_int),
         ("faces", ctypes.POINTER(ctypes.c_double) * 3),
+        ("pw_osc", ctypes.c_double * 6),
     ]
 
 
@@ -135,9 +137,11 @@ def config(d: dict) -> Config:
     c.model = int(d.get("model", 0))
     uw = d.get("uw", [[0.0] * 3] * 6)
     pw = d.get("pw", [0.0] * 6)
+    pwo = d.get("pw_osc", [0.0] * 6)
     for s in range(6):
         c.bc[s] = int(d["bc"][s])
         c.pw[s] = float(pw[s])
+        c.pw_osc[s] = float(pwo[s])
         for a in range(3):
             c.uw[s][a] = float(uw[s][a])
     # custom face coordinates (mesh kind 2): host float64 arrays, kept alive

@@ -475,7 +475,7 @@ __device__ __forceinline__ void adjw_face_body(const Inst<T>& P, long long fi, c
         face_recon_at<LAT, T, A>(P, phi, co, fo);
         face_force<LAT, T>(P, force, A, co[A], P.m[A].w[co[A]], co, gth, Go);
         neq_capture<LAT, T>(P, A, fo, Go, info);
-        wall_rule<LAT, T>(P, wlo ? 2 * A : 2 * A + 1, fb, info);
+        wall_rule<LAT, T>(P, wlo ? 2 * A : 2 * A + 1, fb, info, gth);
     }
     T rho, u[3];
     face_moments<LAT, T>(P, fb, G, rho, u);
@@ -548,7 +548,7 @@ __device__ __forceinline__ void adjw_face_body(const Inst<T>& P, long long fi, c
 #pragma unroll
                 for (int d = 0; d < D; ++d) ua[d] = P.uw[s][d];
             } else {
-                ra = P.rhow[s];
+                ra = wall_density(P, s, gth);
 #pragma unroll
                 for (int d = 0; d < D; ++d) ua[d] = info.uc[d];
             }

@@ -97,12 +97,15 @@ int validate(const dugks_config* c, std::string& why)
         if (!std::isfinite(c->G[a])) { why = "non-finite acceleration"; return DUGKS_EINVAL; }
     if (!std::isfinite(c->omega) || !std::isfinite(c->phase)) { why = "non-finite omega/phase"; return DUGKS_EINVAL; }
     for (int s = 0; s < 6; ++s) {
-        if (!std::isfinite(c->pw[s])) { why = "non-finite wall pressure"; return DUGKS_EINVAL; }
+        if (!std::isfinite(c->pw[s]) || !std::isfinite(c->pw_osc[s])) {
+            why = "non-finite wall pressure";
+            return DUGKS_EINVAL;
+        }
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(c->uw[s][a])) { why = "non-finite wall velocity"; return DUGKS_EINVAL; }
     }
     for (int s = 0; s < 2 * D; ++s)
-        if (c->bc[s] == DUGKS_NEQ_PRESSURE && c->rho0 + c->pw[s] / c->RT <= 0) {
+        if (c->bc[s] == DUGKS_NEQ_PRESSURE && c->rho0 + (c->pw[s] - std::fabs(c->pw_osc[s])) / c->RT <= 0) {
             why = "wall pressure gives non-positive density";
             return DUGKS_EINVAL;
         }
@@ -247,6 +250,7 @@ void fill_inst(const dugks_config* c, Inst<T>& P, T* met_dev, std::vector<T>& me
     for (int s = 0; s < 6; ++s) {
         for (int a = 0; a < 3; ++a) P.uw[s][a] = (T)(a < D ? c->uw[s][a] : 0.0);
         P.rhow[s] = (T)(c->rho0 + c->pw[s] / c->RT);
+        P.rhowo[s] = (T)(c->pw_osc[s] / c->RT);
     }
     P.omega = c->omega;
     P.phase = c->phase;

@@ -75,6 +75,7 @@ struct Inst {
     T ugn[3], uct[3], ufdx[3];
     T uw[6][3];
     T rhow[6];     // rho0 + p_w / RT (pressure condition)
+    T rhowo[6];    // oscillating part of the wall density: p_w,osc / RT
     T rlo[3], rhi[3]; // ghost(-1) = (1-rlo) phi(0) + rlo phi(1); ghost(n) likewise
     double omega, phase;
     double dtd;    // dt in double (time stamps of the time factor)
@@ -90,6 +91,15 @@ template <typename T>
 __host__ __device__ inline T tfac(const Inst<T>& P, double t)
 {
     return (T)cos(P.omega * t + P.phase);
+}
+
+// density of the pressure condition of Eq. (NEQ) on side s, rho0 +
+// p_w(t) / RT with p_w(t) = p_w + p_w,osc g(t); gth = g at the interface
+// time of the step
+template <typename T>
+__host__ __device__ inline T wall_density(const Inst<T>& P, int s, T gth)
+{
+    return P.rhow[s] + P.rhowo[s] * gth;
 }
 
 // Eq. (icfeq): incompressible equilibrium, xi.u = c (e.u)

@@ -250,7 +250,7 @@ __device__ __forceinline__ void neq_capture(const Inst<T>& P, int a, const T* op
 // Appendix step 5 on a wall face of side s (Eqs. BB, NEQ), in place on the
 // reconstructed values, for the velocities entering the domain.
 template <class LAT, typename T, bool ORIG = false>
-__device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, const NeqInfo<LAT, T>& I)
+__device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, const NeqInfo<LAT, T>& I, T gth)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const int a = s >> 1;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = P.uw[s][d];
     } else {
-        ra = P.rhow[s];
+        ra = wall_density(P, s, gth);
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = I.uc[d];
     }
@@ -353,7 +353,7 @@ __device__ __forceinline__ void axis_fluxes_ct(const Inst<T>& P, const ACC& ph, 
         face_force<LAT, T>(P, force, A, upper ? ca + 1 : ca, upper ? ma.wu : ma.wl, ci, gth, G);
         const bool wall_here = upper ? whi : wlo;
         if (k == 0 && (wlo != whi)) neq_capture<LAT, T, ORIG>(P, A, fb, G, info);
-        if (wall_here) wall_rule<LAT, T, ORIG>(P, upper ? 2 * A + 1 : 2 * A, fb, info);
+        if (wall_here) wall_rule<LAT, T, ORIG>(P, upper ? 2 * A + 1 : 2 * A, fb, info, gth);
         face_original<LAT, T, ORIG>(P, A, fb, G);
         const T s = ma.fdx * P.c;
 #pragma unroll
@@ -451,8 +451,8 @@ __device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const
     const T w = UNI ? T(0.5) : m.w[f];
     recon_at<LAT, T, ACC, A, UNI>(P, ph, off, w, UNI ? P.ugn[A] : m.gn[f], mx, my, mz, fb);
     face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
-    if (wall_lo) wall_rule<LAT, T>(P, 2 * A, fb, info);
-    if (wall_hi) wall_rule<LAT, T>(P, 2 * A + 1, fb, info);
+    if (wall_lo) wall_rule<LAT, T>(P, 2 * A, fb, info, gth);
+    if (wall_hi) wall_rule<LAT, T>(P, 2 * A + 1, fb, info, gth);
     face_original<LAT, T>(P, A, fb, G);
 #pragma unroll
     for (int q = 0; q < Q; ++q)

@@ -244,7 +244,7 @@ __device__ __forceinline__ void neq_capture_half(const Inst<T>& P, const T (&fb)
 // for the lane's velocities entering the domain (sigma e_A sgs < 0)
 template <class LAT, typename T, int A, bool ORIG = false>
 __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&wall)[LAT::REST],
-                                          const NeqHalf<LAT, T>& I, T sg, int sgi)
+                                          const NeqHalf<LAT, T>& I, T sg, int sgi, T gth)
 {
     constexpr int K = LAT::REST, D = LAT::D;
     const int kind = P.bc[s];
@@ -270,7 +270,7 @@ __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = sg * P.uw[s][d];
     } else {
-        ra = P.rhow[s];
+        ra = wall_density(P, s, gth);
 #pragma unroll
         for (int d = 0; d < D; ++d) ua[d] = sg * I.uc[d];
     }
@@ -347,8 +347,8 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
     if constexpr (NOG) G[0] = G[1] = G[2] = T(0);
     else if (LAT::D == 2 && gv.g) face_force_ring<LAT, T>(P, gv, A, off, w, gth, G);
     else face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
-    if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi);
-    if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi);
+    if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi, gth);
+    if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi, gth);
     T rho, u[3];
     moments_half<LAT, T, NOG, ORIG>(P, fb, fr, G, sg, rho, u);
     T us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};

@@ -220,7 +220,8 @@ def step(cfg, f, force=None, t=0.0):
                         ra = rc
                         ua = np.broadcast_to(uw.reshape(D, 1, 1, 1), uc.shape)
                     else:
-                        ra = np.full_like(rc, rho0 + float(cfg.get("pw", [0.0] * 6)[s]) / RT)
+                        p_w = float(cfg.get("pw", [0.0] * 6)[s]) + float(cfg.get("pw_osc", [0.0] * 6)[s]) * g_h
+                        ra = np.full_like(rc, rho0 + p_w / RT)
                         ua = uc
                     new = (equilibrium(ra, ua) + other - equilibrium(rc, uc))[inn]
                 sl = [slice(None)] * 4

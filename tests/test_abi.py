@@ -78,6 +78,9 @@ def test_invalid_configurations_are_rejected(bad):
     (dict(bc=(1, 1, 0, 0, 0, 0), uw=[[float("nan"), 0, 0]] + [[0, 0, 0]] * 5), "non-finite wall velocity"),
     (dict(bc=(2, 2, 0, 0, 0, 0), pw=[-1.0, 0, 0, 0, 0, 0]), "non-positive density"),  # rho0 + p/RT <= 0
     (dict(bc=(0, 0, 1, 2, 0, 0), pw=[0, 0, 0, -0.5, 0, 0]), "non-positive density"),  # a pressure side on y
+    (dict(bc=(2, 2, 0, 0, 0, 0), pw_osc=[0, float("inf"), 0, 0, 0, 0]), "non-finite wall pressure"),
+    # rho0 + (p_w - |p_w,osc|) / RT <= 0: the oscillation's low point
+    (dict(bc=(2, 2, 0, 0, 0, 0), pw=[0.1, 0, 0, 0, 0, 0], pw_osc=[-0.5, 0, 0, 0, 0, 0]), "non-positive density"),
     (dict(mesh=(2, 0, 0)), "custom mesh needs its face coordinates"),
     (dict(mesh=(2, 0, 0), faces=([0.0, 1, 2, 3, 4, 5, 6, 7, 8.5], None, None)), "start at 0 and end at L"),
     (dict(mesh=(2, 0, 0), faces=([0.0, 1, 2, 3, 3, 5, 6, 7, 8], None, None)), "strictly increasing"),

@@ -105,6 +105,34 @@ def test_step_adjoint_walls_match_oracle(name, lat, n, bc, mesh, uw, pw):
         M.dugks_destroy(ctx)
 
 
+@pytest.mark.parametrize("lat,n,bc,mesh", [(9, (40, 17), (2, 2, 3, 3, 0, 0), 0),
+                                           (19, (9, 12, 7), (2, 2, 1, 3, 3, 3), 1)], ids=["q9", "q19"])
+def test_step_adjoint_oscillating_pressure_matches_oracle(lat, n, bc, mesh):
+    # pressure sides whose wall pressure follows the time factor (pw +
+    # pw_osc g(t)): the linearisation point of the wall rule moves with t
+    say(f"[adjoint walls] oscillating pressure q{lat} n={n}")
+    cfg = periodic_cfg(lat, n, mesh, bc=bc, uw=MOVING, pw=[1e-3, -1e-3, 0, 0, 0, 0],
+                       pw_osc=[3e-3, 1e-3, 0, 0, 0, 0])
+    Q, D, shp = M.shape_of(cfg)
+    Gf = field(41, (D,) + shp, 2e-3)
+    f = perturb(42, O.init(cfg, rho=1 + field(43, shp, 0.02), u=field(44, (D,) + shp, 0.05), force=Gf), 1e-2)
+    lam = field(45, f.shape, 1.0)
+    buf = torch.empty((Q,) + shp, dtype=torch.float64, device="cuda")
+    ctx = M.dugks_init(cfg, buf)
+    try:
+        out = torch.empty_like(buf)
+        for t in (0.4, 2.9):
+            gref = np.zeros_like(Gf)
+            ref = O.step_adjoint(cfg, f, lam, force=Gf, t=t, grad_force=gref)
+            gG = torch.zeros((D,) + shp, dtype=torch.float64, device="cuda")
+            M.dugks_step_adjoint(ctx, dev(f), dev(lam), out, dev(Gf), t, gG)
+            torch.cuda.synchronize()
+            assert np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max() < 1e-12
+            assert np.abs(gG.cpu().numpy() - gref).max() / np.abs(gref).max() < 1e-11
+    finally:
+        M.dugks_destroy(ctx)
+
+
 @pytest.mark.parametrize("lat,n,mesh", [(9, (21, 18), 1), (19, (7, 6, 5), 0)])
 def test_general_reverse_pass_on_periodic_meshes(lat, n, mesh, monkeypatch):
     # the wall-capable reverse pass, forced on a periodic mesh, against the

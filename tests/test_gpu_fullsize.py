@@ -247,3 +247,44 @@ def test_cavity_128_spanwise_mirror_symmetry(lat, mesh, re, nsteps):
     say(f"    mirror error {err:.2e}, max |u_z| {np.abs(uz).max():.2e}")
     assert np.abs(uz).max() > 1e-6
     assert err < 1e-12
+
+
+def test_pressure_driven_womersley_40x20():
+    # the pressure-driven channel of Sec. III.C at its printed parameters
+    # (inlet pressure oscillating in time): one period against the oracle,
+    # then the printed bound on the pressure error over the next period
+    from tests.test_oracle_flows import pressure_womersley
+    d, nper, p_exact, u_exact = pressure_womersley(20)
+    cfg = dict(d, dtype="f64")
+    Q, D, shp = M.shape_of(cfg)
+    say(f"[full size] pressure-driven Womersley 40x20, {nper} steps per period")
+    u0 = np.zeros((2,) + shp)
+    u0[0] = u_exact(0.0)[None, :, None]
+    f0 = O.init(d, rho=1.0 + np.broadcast_to(p_exact(0.0)[None, None, :], shp) / d["RT"], u=u0)
+    fa = torch.from_numpy(f0).to("cuda")
+    fb = torch.empty_like(fa)
+    ctx = M.dugks_init(cfg, fb)
+    try:
+        which = M.dugks_run(ctx, fa, fb, nper, None, 0.0)
+        if which:
+            fa, fb = fb, fa
+        torch.cuda.synchronize()
+        ref = O.run(d, f0, nper)
+        err = rel_linf(fa.cpu().numpy(), ref)
+        say(f"    after one period: rel L-inf {err:.2e}")
+        assert err < 1e-10
+        t, sums = nper * d["dt"], np.zeros(2)
+        for _ in range(8):
+            which = M.dugks_run(ctx, fa, fb, nper // 8, None, t)
+            if which:
+                fa, fb = fb, fa
+            t += (nper // 8) * d["dt"]
+            torch.cuda.synchronize()
+            _, u, p, _ = O.moments(d, fa.cpu().numpy(), t=t)
+            pa = np.broadcast_to(p_exact(t)[None, None, :], shp)
+            sums += [((p - pa) ** 2).sum(), (pa ** 2).sum()]
+        ep = np.sqrt(sums[0] / sums[1])
+        say(f"    E(p) over the period {100 * ep:.3f} %")
+        assert ep < 0.0042
+    finally:
+        M.dugks_destroy(ctx)

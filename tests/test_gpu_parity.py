@@ -134,6 +134,10 @@ CASES = [
                                                                        [0.05, 0, 0], [0, 0, 0], [0, 0, 0]],
        pw=[0, 0, 1e-3, 0, 0, 0], G=(1e-4, 2e-4, 0), force_field=True, mesh=(0, 1, 0), k_stretch=1.0, dt=0.3),
     c2("d2q9-minimal", (1, 2), (0, 0, 1, 1, 0, 0), uw=LID),
+    # inlet/outlet pressures following the time factor (pw + pw_osc g(t)),
+    # without acceleration (the source-free instances)
+    c2("d2q9-pressure-osc-bb", (48, 17), (2, 2, 3, 3, 0, 0), pw=[1e-3, 0, 0, 0, 0, 0],
+       pw_osc=[-3e-3, 1e-3, 0, 0, 0, 0], omega=0.05, phase=0.4),
     c2("d2q9-custom-faces", (29, 23), (1, 3, 1, 2, 0, 0), uw=LID, pw=[0, 0, 0, 1e-3, 0, 0], mesh=(2, 2, 0),
        faces=(custom_faces(1, 29, 29.0), custom_faces(2, 23, 23.0), None), dt=0.25, G=(1e-4, 0, 0),
        force_field=True),
@@ -147,6 +151,8 @@ CASES = [
     c3("d3q19-mixed", (12, 9, 11), (2, 2, 1, 3, 0, 0), pw=[2e-3, 0, 0, 0, 0, 0], uw=LID3, mesh=(0, 1, 0),
        k_stretch=1.2, dt=0.3),
     c3("d3q19-minimal", (2, 2, 2), (1, 1, 3, 3, 1, 1), uw=LID3),
+    c3("d3q19-pressure-osc", (12, 9, 11), (2, 2, 3, 3, 1, 1), pw=[0, 1e-3, 0, 0, 0, 0],
+       pw_osc=[2e-3, -1e-3, 0, 0, 0, 0], omega=0.1, uw=LID3, mesh=(0, 1, 0), k_stretch=1.2, dt=0.3),
     c3("d3q19-custom-faces", (14, 11, 12), (1,) * 6, uw=LID3, mesh=(2, 2, 2), dt=0.25,
        faces=(custom_faces(3, 14, 14.0), custom_faces(4, 11, 11.0), custom_faces(5, 12, 12.0))),
     # degenerate periodic axes: a march axis of one plane (the plane ring

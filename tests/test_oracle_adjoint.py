@@ -91,6 +91,21 @@ def test_step_adjoint_dot_product_walls(lat, bc, stretch, uw, pw):
     assert np.vdot(vg, gG) == pytest.approx(np.vdot(jg, w), rel=1e-7)
 
 
+@pytest.mark.parametrize("lat,bc", [(9, (2, 2, 3, 3, 0, 0)), (19, (2, 2, 1, 3, 3, 3))], ids=["q9", "q19"])
+def test_step_adjoint_dot_product_oscillating_pressure(lat, bc):
+    # pressure sides following the time factor (pw + pw_osc g(t)), at two
+    # times of the oscillation
+    d, f, Gf = wall_setup(lat, bc, 1, MOVING, (1e-3, -1e-3, 0, 0, 0, 0))
+    d["pw_osc"] = [3e-3, 1e-3, 0, 0, 0, 0]
+    v = field(45, f.shape, 1.0)
+    w = field(46, f.shape, 1.0)
+    eps = 1e-5
+    for t in (0.4, 2.9):
+        jv = (O.step(d, f + eps * v, Gf, t) - O.step(d, f - eps * v, Gf, t)) / (2 * eps)
+        jtw = O.step_adjoint(d, f, w, force=Gf, t=t)
+        assert np.vdot(v, jtw) == pytest.approx(np.vdot(jv, w), rel=5e-9)
+
+
 DEGENERATE = [
     (9, (1, 5, 1), (0, 0, 1, 1, 0, 0)),       # one-column periodic axis, NEQ walls
     (19, (4, 3, 1), (1, 1, 3, 3, 0, 0)),      # one-plane periodic axis

@@ -195,3 +195,65 @@ def test_periodic_flow_table_recipe():
         assert amp > 1.0  # the steady velocity is larger than the analytic one
     assert 1.8 < np.log2(errs[16][0] / errs[32][0]) < 2.2
     assert 1.6 < np.log2(errs[16][1] / errs[32][1]) < 2.2
+
+
+def pressure_womersley(N):
+    # Sec. III.C: the channel 0 <= x <= 2, 0 <= y <= 1 on a 2N x N mesh,
+    # NEQ pressure inlet/outlet, bounce-back walls, rho0 = 1, nu = 1e-3,
+    # G = 1e-3, RT = 16/3, CFL 0.5, period T = 100 (alpha = 3.963).  The
+    # outlet holds p_out = 0 and the inlet p_out - Lx G cos(omega t), the
+    # pressure of Eq. (Wom_AS_Pressure) at x = 0, i.e. dP/dx = G cos(omega t)
+    Lx, Ly, nu, G, RT, T = 2.0, 1.0, 1e-3, 1e-3, 16.0 / 3.0, 100.0
+    omega = 2 * np.pi / T
+    d = dict(lattice=9, n=(2 * N, N, 1), L=(Lx, Ly, 1.0), rho0=1.0, RT=RT, tau=nu / RT,
+             dt=0.5 * (Ly / N) / np.sqrt(3 * RT), bc=(O.NEQ_PRESSURE, O.NEQ_PRESSURE, O.BOUNCE_BACK, O.BOUNCE_BACK,
+                                                       0, 0),
+             pw=[0.0] * 6, pw_osc=[-Lx * G, 0, 0, 0, 0, 0], omega=omega, phase=0.0)
+    nper = int(round(T / d["dt"]))
+    d["dt"] = T / nper
+    x, y = O.mesh(d, 0)[1][1:-1], O.mesh(d, 1)[1][1:-1]
+
+    def p_exact(t):
+        return -(Lx - x) * G * np.cos(omega * t)
+
+    def u_exact(t):
+        # a pressure gradient +G cos(omega t) drives like a force -G cos(omega t)
+        return womersley_u(y, t, -G, omega, nu, Ly)
+
+    return d, nper, p_exact, u_exact
+
+
+def pressure_womersley_errors(N, periods):
+    # start from the analytic pressure and velocity (as the paper does), run
+    # `periods` periods, then E(p) and E(u) as L2 relative errors over the
+    # eight times nT/8 of one more period (over the whole period: the
+    # pressure passes through zero at T/4 and 3T/4)
+    d, nper, p_exact, u_exact = pressure_womersley(N)
+    D, Q, shp = O.dims(d)
+    u0 = np.zeros((2,) + shp)
+    u0[0] = u_exact(0.0)[None, :, None]
+    f = O.init(d, rho=1.0 + np.broadcast_to(p_exact(0.0)[None, None, :], shp) / d["RT"], u=u0)
+    f = O.run(d, f, periods * nper)
+    t = periods * nper * d["dt"]
+    sums = np.zeros(4)
+    for _ in range(8):
+        f = O.run(d, f, nper // 8, t0=t)
+        t += (nper // 8) * d["dt"]
+        _, u, p, _ = O.moments(d, f, t=t)
+        pa = np.broadcast_to(p_exact(t)[None, None, :], shp)
+        ua = np.broadcast_to(u_exact(t)[None, :, None], shp)
+        sums += [((p - pa) ** 2).sum(), (pa ** 2).sum(), ((u[0] - ua) ** 2).sum(), (ua ** 2).sum()]
+        assert np.abs(u[1]).max() < 2e-2 * np.abs(ua).max() + 1e-6
+    return np.sqrt(sums[0] / sums[1]), np.sqrt(sums[2] / sums[3])
+
+
+def test_pressure_driven_womersley_of_the_paper():
+    # the printed bound: the relative pressure error over the period stays
+    # under 0.42 % (Sec. III.C); the velocity follows the closed form and
+    # converges under refinement (2.0 % at 40 x 20, 0.57 % at 80 x 40)
+    ep20, eu20 = pressure_womersley_errors(20, 1)
+    assert ep20 < 0.0042
+    assert eu20 < 0.03
+    ep40, eu40 = pressure_womersley_errors(40, 1)
+    assert ep40 < ep20
+    assert eu20 / eu40 > 3.0

@@ -113,6 +113,11 @@ RESTATE = [
     cfg(19, (3, 4, 5), (0,) * 6, mesh=(1, 1, 1), ff=1),
     cfg(19, (3, 4, 5), (1,) * 6, uw=UW, mesh=(1, 1, 1), model=1),
     cfg(27, (3, 4, 5), (1, 1, 3, 3, 2, 2), uw=UW, pw=[0, 0, 0, 0, 1e-3, 0], mesh=(1, 1, 1), ff=1),
+    # wall pressures following the time factor (pw + pw_osc g(t))
+    cfg(9, (4, 3, 1), (2, 2, 3, 3, 0, 0), uw=UW, pw=[1e-3, 0, 0, 0, 0, 0], pw_osc=[-2e-3, 5e-4, 0, 0, 0, 0],
+        omega=0.4, phase=0.3, mesh=(1, 0, 0)),
+    cfg(19, (3, 4, 5), (0, 0, 3, 3, 2, 2), uw=UW, pw=[0, 0, 0, 0, 1e-3, 0], pw_osc=[0, 0, 0, 0, -1e-3, 2e-3],
+        omega=0.5, mesh=(0, 1, 1), G=(1e-3, 0, 0)),
 ]
 
 
