@@ -26,7 +26,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
        [--mesh uniform|tanh] [--re 100] [--n 128] [--no-cpu-baseline]
        [--no-extras]
        python bench.py --cavity-re12000   (the unsteady 2-D cavity of Sec. III)
-       python bench.py --adjoint-only     (adjoint vs forward step, periodic and walled 256^2)
+       python bench.py --adjoint-only     (adjoint vs forward step, periodic and walled 256^2, periodic 1024^2)
        python bench.py --summarize-counters FETCH_DIR WRITE_DIR
          (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output of
           `bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-extras
@@ -501,7 +501,8 @@ def main():
         print(json.dumps(bench_cavity12000(tuple(args.re12000_sizes))))
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": bench_adjoint(), "adjoint_walls": bench_adjoint(walls=True)}))
+        print(json.dumps({"adjoint": bench_adjoint(), "adjoint_walls": bench_adjoint(walls=True),
+                          "adjoint_1024": bench_adjoint(1024, steps=20, full_steps=0)}))
         return
     cfg = cavity_cfg(args.n, args.dtype, args.mesh, args.re, lattice=args.lattice)
     Q, D, shp = M.shape_of(cfg)
@@ -607,6 +608,7 @@ def main():
         also["batched_f32"] = bench_batched("f32")
         also["adjoint"] = bench_adjoint()
         also["adjoint_walls"] = bench_adjoint(walls=True)
+        also["adjoint_1024"] = bench_adjoint(1024, steps=20, full_steps=0)
         res["also"] = also
         res["context"] = device_context(achieved)
     if not args.no_cpu_baseline:

@@ -17,6 +17,9 @@
 //   pass C (per cell): phi_hat += cp_t(s-t) d_hat_t(s-t) + cm_t(s+t) d_hat_t(s+t);
 //     reverse of Eq. (f_bar_+) and of the macroscopic recovery -> lam_n and
 //     the force-field gradient (cell term at t_n, face terms at t_n + h).
+// For the 2-D sets passes B and C run as one launch over cell tiles whose
+// d_hat (halo included) is formed in LDS, so a step reads and writes main
+// memory in three passes (phi, faces, cells) instead of four.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,26 +69,20 @@ __device__ __forceinline__ Partials<LAT, T> partials(int q, T rho, const T* u, c
 template <typename T>
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// pass A: adjoint of the lower face of cell R along axis A
-template <class LAT, typename T, int A>
-__device__ __forceinline__ void adj_face_body(const Inst<T>& P, long long cidx, const T* __restrict__ phi,
+// pass A: adjoint of the lower face of cell R (coordinates ci, index cidx)
+// along axis A; ph reads f-bar-plus around the cell
+template <class LAT, typename T, int A, class ACC>
+__device__ __forceinline__ void adj_face_core(const Inst<T>& P, const int* ci, long long cidx, const ACC& ph,
                                               const T* __restrict__ force, const T* __restrict__ lam, T gth,
                                               T* __restrict__ fa, T* __restrict__ ga)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    int ci[3];
-    ci[0] = (int)(cidx % P.n[0]);
-    const long long r = cidx / P.n[0];
-    ci[1] = (int)(r % P.n[1]);
-    ci[2] = (int)(r / P.n[1]);
-    GlobalPhi<LAT, T> ph{phi, P.ne, ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]), (long long)P.E[0],
-                         (long long)P.E[0] * P.E[1]};
     const CellMetric<T> cx = load_metric(P, 0, ci[0]);
     const CellMetric<T> cy = load_metric(P, 1, ci[1]);
     const CellMetric<T> cz = D == 3 ? load_metric(P, 2, ci[2]) : cy;
     const CellMetric<T>& ma = A == 0 ? cx : (A == 1 ? cy : cz);
     T fb[Q], G[3];
-    recon_face_ct<LAT, T, GlobalPhi<LAT, T>, A>(P, ph, false, ma, cx, cy, cz, fb);
+    recon_face_ct<LAT, T, ACC, A>(P, ph, false, ma, cx, cy, cz, fb);
     face_force<LAT, T>(P, force, A, ci[A], ma.wl, ci, gth, G);
     T rho, u[3];
     face_moments<LAT, T>(P, fb, G, rho, u);
@@ -127,11 +124,28 @@ __device__ __forceinline__ void adj_face_body(const Inst<T>& P, long long cidx, 
     for (int d = 0; d < D; ++d) ga[((long long)A * D + d) * P.nc + cidx] = Gb[d];
 }
 
+// the same with f-bar-plus from the ghost-extended array in memory
+template <class LAT, typename T, int A>
+__device__ __forceinline__ void adj_face_body(const Inst<T>& P, long long cidx, const T* __restrict__ phi,
+                                              const T* __restrict__ force, const T* __restrict__ lam, T gth,
+                                              T* __restrict__ fa, T* __restrict__ ga)
+{
+    int ci[3];
+    ci[0] = (int)(cidx % P.n[0]);
+    const long long r = cidx / P.n[0];
+    ci[1] = (int)(r % P.n[1]);
+    ci[2] = (int)(r / P.n[1]);
+    GlobalPhi<LAT, T> ph{phi, P.ne, ext_idx<LAT, T>(P, ci[0], ci[1], ci[2]), (long long)P.E[0],
+                         (long long)P.E[0] * P.E[1]};
+    adj_face_core<LAT, T, A>(P, ci, cidx, ph, force, lam, gth, fa, ga);
+}
+
 template <class LAT, typename T>
 __global__ __launch_bounds__(256) void k_adj_face(const Inst<T>* __restrict__ Pp, const T* __restrict__ phi,
                                                   const T* __restrict__ force, const T* __restrict__ lam, T gth,
                                                   T* __restrict__ fa, T* __restrict__ ga)
 {
+    // one axis per grid row (blockIdx.y)
     const Inst<T>& P = *Pp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nc) return;
@@ -196,43 +210,17 @@ __global__ __launch_bounds__(256) void k_adj_cell1(const Inst<T>* __restrict__ P
     for (int q = 0; q < Q; ++q) ph_out[(long long)q * P.nc + cidx] = phat[q];
 }
 
-// pass C
+// reverse of Eq. (f_bar_+) at the cell and of the macroscopic recovery
+// (step 1), given the cell's complete phi-hat: lam_n = phi-hat terms - 1/3
+// lam_{n+1} (Eq. f_tilde_+), and the force-field gradient (cell term at t_n,
+// face terms at t_n + h from the face adjoints ga)
 template <class LAT, typename T>
-__global__ __launch_bounds__(256) void k_adj_cell2(const Inst<T>* __restrict__ Pp, const T* __restrict__ f,
-                                                   const T* __restrict__ force, const T* __restrict__ lam,
-                                                   const T* __restrict__ ph_in, const T* __restrict__ dt_in,
-                                                   const T* __restrict__ ga, T gt, T gth, T* __restrict__ lam_out,
-                                                   T* __restrict__ grad_force)
+__device__ __forceinline__ void adj_cell_finish(const Inst<T>& P, const int* ci, long long cidx, T (&phat)[LAT::Q],
+                                                const T* __restrict__ f, const T* __restrict__ force,
+                                                const T* __restrict__ lam, const T* __restrict__ ga, T gt, T gth,
+                                                T* __restrict__ lam_out, T* __restrict__ grad_force)
 {
     constexpr int Q = LAT::Q, D = LAT::D;
-    const Inst<T>& P = *Pp;
-    const long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cidx >= P.nc) return;
-    int ci[3];
-    ci[0] = (int)(cidx % P.n[0]);
-    const long long r = cidx / P.n[0];
-    ci[1] = (int)(r % P.n[1]);
-    ci[2] = (int)(r / P.n[1]);
-    const long long stride = (long long)Q * P.nc;
-    T phat[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) phat[q] = ph_in[(long long)q * P.nc + cidx];
-#pragma unroll
-    for (int t = 0; t < D; ++t) {
-        int cm_[3] = {ci[0], ci[1], ci[2]}, cp_[3] = {ci[0], ci[1], ci[2]};
-        cm_[t] = wrapc<T>(ci[t] - 1, P.n[t]);
-        cp_[t] = wrapc<T>(ci[t] + 1, P.n[t]);
-        const long long im = int_idx(P, cm_[0], cm_[1], cm_[2]), ip = int_idx(P, cp_[0], cp_[1], cp_[2]);
-        const T cpm = P.m[t].cp[cm_[t]];  // cp of the cell below: its d_t uses this cell as +t neighbour
-        const T cmp = P.m[t].cm[cp_[t]];  // cm of the cell above
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (LAT::e(q, t) == 0) continue;
-            phat[q] += cpm * dt_in[t * stride + (long long)q * P.nc + im] +
-                       cmp * dt_in[t * stride + (long long)q * P.nc + ip];
-        }
-    }
-    // forward cell quantities (step 1)
     const T invRT = T(1) / P.RT;
     T fv[Q], rho = T(0), j[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -290,6 +278,244 @@ __global__ __launch_bounds__(256) void k_adj_cell2(const Inst<T>* __restrict__ P
             grad_force[(long long)d * P.nc + cidx] += gsum;
         }
     }
+}
+
+// pass C
+template <class LAT, typename T>
+__global__ __launch_bounds__(256) void k_adj_cell2(const Inst<T>* __restrict__ Pp, const T* __restrict__ f,
+                                                   const T* __restrict__ force, const T* __restrict__ lam,
+                                                   const T* __restrict__ ph_in, const T* __restrict__ dt_in,
+                                                   const T* __restrict__ ga, T gt, T gth, T* __restrict__ lam_out,
+                                                   T* __restrict__ grad_force)
+{
+    constexpr int Q = LAT::Q, D = LAT::D;
+    const Inst<T>& P = *Pp;
+    const long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= P.nc) return;
+    int ci[3];
+    ci[0] = (int)(cidx % P.n[0]);
+    const long long r = cidx / P.n[0];
+    ci[1] = (int)(r % P.n[1]);
+    ci[2] = (int)(r / P.n[1]);
+    const long long stride = (long long)Q * P.nc;
+    T phat[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) phat[q] = ph_in[(long long)q * P.nc + cidx];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        int cm_[3] = {ci[0], ci[1], ci[2]}, cp_[3] = {ci[0], ci[1], ci[2]};
+        cm_[t] = wrapc<T>(ci[t] - 1, P.n[t]);
+        cp_[t] = wrapc<T>(ci[t] + 1, P.n[t]);
+        const long long im = int_idx(P, cm_[0], cm_[1], cm_[2]), ip = int_idx(P, cp_[0], cp_[1], cp_[2]);
+        const T cpm = P.m[t].cp[cm_[t]];  // cp of the cell below: its d_t uses this cell as +t neighbour
+        const T cmp = P.m[t].cm[cp_[t]];  // cm of the cell above
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (LAT::e(q, t) == 0) continue;
+            phat[q] += cpm * dt_in[t * stride + (long long)q * P.nc + im] +
+                       cmp * dt_in[t * stride + (long long)q * P.nc + ip];
+        }
+    }
+    adj_cell_finish<LAT, T>(P, ci, cidx, phat, f, force, lam, ga, gt, gth, lam_out, grad_force);
+}
+
+// passes B and C in one launch for the 2-D sets: a workgroup owns a tile of
+// ADJ_TX x ADJ_TY cells, one per thread.  Each thread forms its cell's local
+// phi-hat (kept in registers) and d_hat (to LDS); the d_hat of the one-cell
+// halo, which the tile's edge cells need from their outer neighbours, is
+// formed velocity by velocity by all threads; then each cell adds its
+// neighbours' d_hat from LDS.  No phi-hat or d_hat arrays in memory; the
+// same operations in the same order as the two passes.
+constexpr int ADJ_TX = 32, ADJ_TY = 8;
+
+// slot of velocity q among those with e(q, t) != 0, their count, and the
+// velocity of a slot
+template <class LAT>
+__host__ __device__ constexpr int adj_slot(int q, int t)
+{
+    int s = 0;
+    for (int r = 0; r < q; ++r)
+        if (LAT::e(r, t) != 0) ++s;
+    return s;
+}
+template <class LAT>
+__host__ __device__ constexpr int adj_nslot(int t)
+{
+    return adj_slot<LAT>(LAT::Q, t);
+}
+template <class LAT>
+__host__ __device__ constexpr int adj_q_of_slot(int t, int slot)
+{
+    for (int q = 0; q < LAT::Q; ++q)
+        if (LAT::e(q, t) != 0 && adj_slot<LAT>(q, t) == slot) return q;
+    return -1;
+}
+
+__device__ __forceinline__ int wrap_any(int i, int n) { return ((i % n) + n) % n; }
+
+template <class LAT, typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, ADJ_TX * ADJ_TY), amdgpu_waves_per_eu(4))) void k_adj_cell_tile(
+    const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force, const T* __restrict__ lam,
+    const T* __restrict__ fa, const T* __restrict__ ga, T gt, T gth, int tiles_x, T* __restrict__ lam_out,
+    T* __restrict__ grad_force)
+{
+    static_assert(LAT::D == 2, "2-D sets only");
+    constexpr int Q = LAT::Q, D = 2;
+    constexpr int RX = ADJ_TX + 2, RY = ADJ_TY + 2, NR = RX * RY, NC = ADJ_TX * ADJ_TY;
+    constexpr int NS0 = adj_nslot<LAT>(0), NS1 = adj_nslot<LAT>(1);
+    constexpr int NS = NS0 > NS1 ? NS0 : NS1;
+    __shared__ T dts[D][NS][NR];  // d_hat_t of the region's cells, velocities with e_t != 0
+    const Inst<T>& P = *Pp;
+    const long long stride = (long long)Q * P.nc;
+    const int x0 = (int)(blockIdx.x % tiles_x) * ADJ_TX, y0 = (int)(blockIdx.x / tiles_x) * ADJ_TY;
+    const int tx = (int)threadIdx.x % ADJ_TX, ty = (int)threadIdx.x / ADJ_TX;
+    const int rc = (ty + 1) * RX + (tx + 1);  // this thread's cell in the region
+    // the thread's cell (the wrapped coordinates past a ragged mesh edge:
+    // there the slot serves as halo of the cells before it)
+    const int ci[3] = {wrap_any(x0 + tx, P.n[0]), wrap_any(y0 + ty, P.n[1]), 0};
+    const bool own = x0 + tx < P.n[0] && y0 + ty < P.n[1];
+    const long long cidx = int_idx(P, ci[0], ci[1], ci[2]);
+    T phat[Q];
+    // (a one-trip loop: a scheduling region of its own, which keeps the
+    // compiler from hoisting later stages' loads into it; fewer registers)
+#pragma unroll 1
+    for (int once = (int)threadIdx.x; once < NC; once += NC) {
+        T psi[D][Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) phat[q] = T(4.0 / 3.0) * lam[(long long)q * P.nc + cidx];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            asm volatile("" ::: "memory");  // one axis's face adjoints in flight at a time
+            const CellMetric<T> m = load_metric(P, a, ci[a]);
+            int cu[3] = {ci[0], ci[1], ci[2]};
+            cu[a] = wrapc<T>(ci[a] + 1, P.n[a]);
+            const long long uidx = int_idx(P, cu[0], cu[1], cu[2]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const T flo = fa[a * stride + (long long)q * P.nc + cidx];  // lower face (this cell is R)
+                const T fup = fa[a * stride + (long long)q * P.nc + uidx];  // upper face (this cell is L)
+                psi[a][q] = m.wl * flo + (T(1) - m.wu) * fup;
+                phat[q] += psi[a][q] + T(LAT::e(q, a)) * P.h * P.c * (m.gu * fup - m.gl * flo);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const CellMetric<T> m = load_metric(P, t, ci[t]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                T dh = T(0);
+                if (LAT::e(q, t) != 0) {
+                    T s = T(0);
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        if (a != t) s += psi[a][q];
+                    dh = -P.h * P.c * T(LAT::e(q, t)) * s;
+                    dts[t][adj_slot<LAT>(q, t)][rc] = dh;
+                }
+                phat[q] += m.c0 * dh;
+            }
+        }
+    }
+    // halo: the left/right columns need d_hat_0, the bottom/top rows d_hat_1
+    // (corners are nobody's neighbour); one velocity per item.  (The memory
+    // clobbers keep the compiler from hoisting the loads of later stages
+    // here, which would only hold registers.)
+    asm volatile("" ::: "memory");
+    constexpr int NX_ITEMS = 2 * ADJ_TY * NS0, N_ITEMS = NX_ITEMS + 2 * ADJ_TX * NS1;
+#pragma unroll 1
+    for (int i = (int)threadIdx.x; i < N_ITEMS; i += NC) {
+        int t, slot, rx, ry;
+        if (i < NX_ITEMS) {
+            t = 0;
+            slot = i % NS0;
+            const int k = i / NS0;  // 0 .. 2 ADJ_TY - 1
+            rx = (k / ADJ_TY) ? RX - 1 : 0;
+            ry = 1 + k % ADJ_TY;
+        } else {
+            t = 1;
+            const int j = i - NX_ITEMS;
+            slot = j % NS1;
+            const int k = j / NS1;  // 0 .. 2 ADJ_TX - 1
+            ry = (k / ADJ_TX) ? RY - 1 : 0;
+            rx = 1 + k % ADJ_TX;
+        }
+        const int a = 1 - t;
+        const int q = t == 0 ? adj_q_of_slot<LAT>(0, slot) : adj_q_of_slot<LAT>(1, slot);
+        const int hc[3] = {wrap_any(x0 - 1 + rx, P.n[0]), wrap_any(y0 - 1 + ry, P.n[1]), 0};
+        int hu[3] = {hc[0], hc[1], 0};
+        hu[a] = wrapc<T>(hc[a] + 1, P.n[a]);
+        const long long hidx = int_idx(P, hc[0], hc[1], hc[2]), huidx = int_idx(P, hu[0], hu[1], hu[2]);
+        const T wl = P.m[a].w[hc[a]], wu = P.m[a].w[hc[a] + 1];
+        const T psi = wl * fa[a * stride + (long long)q * P.nc + hidx] +
+                      (T(1) - wu) * fa[a * stride + (long long)q * P.nc + huidx];
+        T s = T(0);
+        s += psi;
+        const int e = t == 0 ? LAT::ex(q) : LAT::ey(q);
+        dts[t][slot][ry * RX + rx] = -P.h * P.c * T(e) * s;
+    }
+    __syncthreads();
+    asm volatile("" ::: "memory");
+    if (!own) return;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const int rm = rc - (t == 0 ? 1 : RX), rp = rc + (t == 0 ? 1 : RX);
+        const T cpm = P.m[t].cp[wrapc<T>(ci[t] - 1, P.n[t])];  // cp of the cell below
+        const T cmp = P.m[t].cm[wrapc<T>(ci[t] + 1, P.n[t])];  // cm of the cell above
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (LAT::e(q, t) == 0) continue;
+            phat[q] += cpm * dts[t][adj_slot<LAT>(q, t)][rm] + cmp * dts[t][adj_slot<LAT>(q, t)][rp];
+        }
+    }
+    adj_cell_finish<LAT, T>(P, ci, cidx, phat, f, force, lam, ga, gt, gth, lam_out, grad_force);
+}
+
+// f-bar-plus of a tile's region in LDS, laid out [q][region cell] with rows
+// of RX cells; rc: the thread's cell (the accessor recon_face_ct reads)
+template <typename T, int RX, int NR>
+struct TilePhi {
+    const T* s;
+    int rc;
+    __device__ __forceinline__ int base(int ox, int oy, int) const { return rc + ox + oy * RX; }
+    __device__ __forceinline__ int up(int t) const { return t == 0 ? 1 : RX; }
+    __device__ __forceinline__ int dn(int t) const { return up(t); }
+    __device__ __forceinline__ T get(int q, int b) const { return s[q * NR + b]; }
+};
+
+// the f-bar-plus pass and pass A in one launch for the 2-D sets: a workgroup
+// forms f-bar-plus (Eq. f_bar_+, from f_n at t_n) of its tile of ADJ_TX x
+// ADJ_TY cells and their one-cell halo (periodic wrap) in LDS, then each
+// thread takes the lower faces of both axes of its cell from there (no
+// f-bar-plus array in memory)
+template <class LAT, typename T>
+__global__ __launch_bounds__(ADJ_TX * ADJ_TY) void k_adj_face_tile(
+    const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force, const T* __restrict__ lam,
+    T gt, T gth, int tiles_x, T* __restrict__ fa, T* __restrict__ ga)
+{
+    static_assert(LAT::D == 2, "2-D sets only");
+    constexpr int Q = LAT::Q;
+    constexpr int RX = ADJ_TX + 2, RY = ADJ_TY + 2, NR = RX * RY, NC = ADJ_TX * ADJ_TY;
+    __shared__ T phs[Q * NR];
+    const Inst<T>& P = *Pp;
+    const int x0 = (int)(blockIdx.x % tiles_x) * ADJ_TX, y0 = (int)(blockIdx.x / tiles_x) * ADJ_TY;
+#pragma unroll 1
+    for (int r = (int)threadIdx.x; r < NR; r += NC) {
+        const int cx = wrap_any(x0 - 1 + r % RX, P.n[0]), cy = wrap_any(y0 - 1 + r / RX, P.n[1]);
+        T out[Q];
+        phi_cell<LAT, T>(P, f, force, int_idx(P, cx, cy, 0), gt, out);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) phs[q * NR + r] = out[q];
+    }
+    __syncthreads();
+    asm volatile("" ::: "memory");
+    const int tx = (int)threadIdx.x % ADJ_TX, ty = (int)threadIdx.x / ADJ_TX;
+    if (x0 + tx >= P.n[0] || y0 + ty >= P.n[1]) return;
+    const int ci[3] = {x0 + tx, y0 + ty, 0};
+    const long long cidx = int_idx(P, ci[0], ci[1], 0);
+    const TilePhi<T, RX, NR> ph{phs, (ty + 1) * RX + (tx + 1)};
+    adj_face_core<LAT, T, 0>(P, ci, cidx, ph, force, lam, gth, fa, ga);
+    asm volatile("" ::: "memory");
+    adj_face_core<LAT, T, 1>(P, ci, cidx, ph, force, lam, gth, fa, ga);
 }
 
 // reverse of the initial state (rho = rho0)
@@ -1005,31 +1231,42 @@ static int adjoint_step(dugks_ctx* ctx, const Inst<T>& P, const void* fn, const 
 {
     constexpr int Q = LAT::Q, D = LAT::D;
     const size_t es = sizeof(T);
-    const size_t need = (size_t)P.ne * Q * es              // phi (extended)
-                        + (size_t)D * Q * P.nc * es          // face adjoints
+    // 2-D sets: two tiled launches (f-bar-plus with pass A, passes B with C)
+    constexpr bool tiled = D == 2;
+    const size_t need = (size_t)D * Q * P.nc * es            // face adjoints
                         + (size_t)D * D * P.nc * es          // face force adjoints
-                        + (size_t)Q * P.nc * es              // phi_hat partial
-                        + (size_t)D * Q * P.nc * es;         // d_hat
+                        + (tiled ? 0 : (size_t)P.ne * Q * es)        // phi (extended)
+                        + (tiled ? 0 : (size_t)Q * P.nc * es)        // phi_hat partial
+                        + (tiled ? 0 : (size_t)D * Q * P.nc * es);   // d_hat
     void* work = nullptr;
     const int src = adjoint_scratch(ctx, need, stat, &work);
     if (src != DUGKS_OK) return src;
-    T* base = (T*)work;
-    T* phi = base;
-    T* fa = phi + (size_t)P.ne * Q;
+    T* fa = (T*)work;
     T* ga = fa + (size_t)D * Q * P.nc;
-    T* ph = ga + (size_t)D * D * P.nc;
-    T* dh = ph + (size_t)Q * P.nc;
     const Inst<T>* Pd = (const Inst<T>*)ctx->inst_dev;
     const T gt = tfac(P, t), gth = tfac(P, t + 0.5 * (double)ctx->cfg.dt);
-    hipLaunchKernelGGL((k_phi_adj<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, (const T*)fn, (const T*)force,
-                       phi, gt);
-    hipLaunchKernelGGL((k_adj_face<LAT, T>), dim3(nb256(P.nc), D), dim3(256), 0, st, Pd, (const T*)phi,
-                       (const T*)force, (const T*)lam_np1, gth, fa, ga);
-    hipLaunchKernelGGL((k_adj_cell1<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)lam_np1,
-                       (const T*)fa, ph, dh);
-    hipLaunchKernelGGL((k_adj_cell2<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)fn,
-                       (const T*)force, (const T*)lam_np1, (const T*)ph, (const T*)dh, (const T*)ga, gt, gth,
-                       (T*)lam_n, (T*)grad_force);
+    if constexpr (tiled) {
+        const int tiles_x = (P.n[0] + ADJ_TX - 1) / ADJ_TX, tiles_y = (P.n[1] + ADJ_TY - 1) / ADJ_TY;
+        const dim3 grid((unsigned)(tiles_x * tiles_y)), block(ADJ_TX * ADJ_TY);
+        hipLaunchKernelGGL((k_adj_face_tile<LAT, T>), grid, block, 0, st, Pd, (const T*)fn, (const T*)force,
+                           (const T*)lam_np1, gt, gth, tiles_x, fa, ga);
+        hipLaunchKernelGGL((k_adj_cell_tile<LAT, T>), grid, block, 0, st, Pd, (const T*)fn, (const T*)force,
+                           (const T*)lam_np1, (const T*)fa, (const T*)ga, gt, gth, tiles_x, (T*)lam_n,
+                           (T*)grad_force);
+    } else {
+        T* phi = ga + (size_t)D * D * P.nc;
+        T* ph = phi + (size_t)P.ne * Q;
+        T* dh = ph + (size_t)Q * P.nc;
+        hipLaunchKernelGGL((k_phi_adj<LAT, T>), dim3(nb256(P.ne)), dim3(256), 0, st, Pd, (const T*)fn,
+                           (const T*)force, phi, gt);
+        hipLaunchKernelGGL((k_adj_face<LAT, T>), dim3(nb256(P.nc), D), dim3(256), 0, st, Pd, (const T*)phi,
+                           (const T*)force, (const T*)lam_np1, gth, fa, ga);
+        hipLaunchKernelGGL((k_adj_cell1<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)lam_np1,
+                           (const T*)fa, ph, dh);
+        hipLaunchKernelGGL((k_adj_cell2<LAT, T>), dim3(nb256(P.nc)), dim3(256), 0, st, Pd, (const T*)fn,
+                           (const T*)force, (const T*)lam_np1, (const T*)ph, (const T*)dh, (const T*)ga, gt, gth,
+                           (T*)lam_n, (T*)grad_force);
+    }
     return hip_check(ctx, hipGetLastError(), "adjoint launch");
 }
 
