@@ -475,6 +475,9 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--adjoint-only", action="store_true",
                     help="print only the adjoint figures (periodic and walled D2Q9 256^2) as one JSON line")
+    ap.add_argument("--profile-case", choices=["adjoint1024", "batch64"],
+                    help="a few steps of one extra workload for the profiler (D2Q9 1024^2 periodic adjoint "
+                         "with its forward steps, or the 64-instance FP64 batch), one JSON line")
     ap.add_argument("--cavity-re12000", action="store_true",
                     help="run the Re = 12000 2-D cavity (128^2 and 96^2 to t = 3000, 80^2 to t = 1500; "
                          "about six minutes) and print its JSON line instead of the benchmark")
@@ -499,6 +502,13 @@ def main():
     torch.cuda.init()
     if args.cavity_re12000:
         print(json.dumps(bench_cavity12000(tuple(args.re12000_sizes))))
+        return
+    if args.profile_case == "adjoint1024":
+        print(json.dumps({"adjoint_1024": bench_adjoint(1024, steps=args.steps, warmup=args.warmup,
+                                                         full_steps=0)}))
+        return
+    if args.profile_case == "batch64":
+        print(json.dumps({"batched": bench_batched("f64", steps=args.steps, warmup=args.warmup)}))
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": bench_adjoint(), "adjoint_walls": bench_adjoint(walls=True),
