@@ -240,11 +240,13 @@ int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, cons
  *   lam_n       = (d f_{n+1} / d f_n)^T lam_np1
  *   grad_force += (d f_{n+1} / d G^)^T lam_np1   (nullable, [D])
  * The forward intermediates are recomputed from f_n (no tape).  Fully
- * periodic meshes take a three-pass gather form; meshes with walls a
+ * periodic meshes take a gather form: in 2-D two launches over cell tiles
+ * (f-bar-plus and the interface adjoints; then the cell adjoints, the
+ * neighbours' terms staged in LDS), in 3-D four passes; meshes with walls a
  * gather form over every face and the ghost-extended grid (the ghost rule
- * of step 2 is transposed).  The scratch (about (2 + D) Q values per
- * extended cell plus (Q + D) per face and per cell) is allocated on first
- * use and kept by the context.  lam_n must not alias f_n or lam_np1.  The original-model
+ * of step 2 is transposed).  The scratch (2-D periodic: D (Q + D) values per
+ * cell; otherwise about (2 + D) Q values per extended cell plus (Q + D) per
+ * face and per cell) is allocated on first use and kept by the context.  lam_n must not alias f_n or lam_np1.  The original-model
  * variant and D3Q27 return DUGKS_EUNSUPPORTED.  Asynchronous.
  */
 int dugks_step_adjoint(dugks_ctx* ctx, const void* f_n, const void* force, double t_n,
