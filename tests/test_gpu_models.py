@@ -148,3 +148,37 @@ def test_compressibility_comparison_on_the_gpu():
     assert 0 <= growth_i < 2 * float(ref["growth_incompressible"])
     assert reduction == pytest.approx(float(ref["reduction_at_max"]), abs=0.04)
     assert ec[0] == pytest.approx(ei[0], rel=1e-3)
+
+
+def test_womersley_model_comparison_table_on_the_gpu():
+    # Table Wom_C_IC (Sec. III.C), both models, every forcing level, run on
+    # the GPU through the C ABI: the sixteen E(u) values per level after
+    # three settling periods equal those recorded from the oracle
+    # (tests/golden/table_wom_c_ic_recipe.txt), 64 000 steps per run
+    from tests.test_oracle_models import _wom_recipe
+    R, printed, recorded = _wom_recipe()
+    for G in sorted(recorded):
+        for col, model in ((6, 1), (14, 0)):
+            d, nper, x, y = R.problem(G, model)
+            cfg = dict(d, dtype="f64")
+            fa = torch.from_numpy(R.initial_state(d, x, y, G)).to("cuda")
+            fb = torch.empty_like(fa)
+            ctx = M.dugks_init(cfg, fb)
+            try:
+                which = M.dugks_run(ctx, fa, fb, R.PERIODS * nper, None, 0.0)
+                if which:
+                    fa, fb = fb, fa
+                t, E = R.PERIODS * nper * d["dt"], []
+                for _ in range(8):
+                    which = M.dugks_run(ctx, fa, fb, nper // 8, None, t)
+                    if which:
+                        fa, fb = fb, fa
+                    t += (nper // 8) * d["dt"]
+                    torch.cuda.synchronize()
+                    E.append(R.velocity_error(d, fa.cpu().numpy(), y, t, G))
+            finally:
+                M.dugks_destroy(ctx)
+            want = recorded[G][col:col + 8]
+            print(f"[womersley table] G={G} model={model} E_max {100 * max(E):.4f} % (oracle {100 * want.max():.4f} %)",
+                  flush=True)
+            np.testing.assert_allclose(E, want, rtol=1e-7)
