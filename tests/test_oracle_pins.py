@@ -176,6 +176,33 @@ def test_uniform_state_fixed_point(lat, stretch):
 
 
 @pytest.mark.parametrize("lat", [9, 19, 27])
+@pytest.mark.parametrize("tau,dt", [(0.6, 0.5), (0.05, 0.5), (1e-3, 0.2)])
+def test_homogeneous_relaxation_closed_form(lat, tau, dt):
+    # one periodic cell, no force: the interface fluxes cancel and the step
+    # is the collision alone.  Eqs. (f_bar_+) and (f_tilde_+) then give
+    # f~(n+1) = f~ + (4/3) B1 (feq - f~), B1 = 3h/(2 tau + dt), h = dt/2, with
+    # rho and j unchanged, i.e. the non-equilibrium part decays by the
+    # trapezoidal factor (2 tau - dt)/(2 tau + dt) per step (negative and
+    # close to -1 for tau << dt) -- a closed form independent of the scheme's
+    # transcription.  Planted mistakes each fail it: h for dt in B1's
+    # numerator, 2 tau - dt for 2 tau - h in the f~ coefficient, and 3/2, 1/2
+    # for 4/3, 1/3 in Eq. (f_tilde_+)
+    d = cfg2(n=(1, 1), tau=tau, dt=dt, lattice=lat) if lat == 9 else cfg3(n=(1, 1, 1), tau=tau, dt=dt, lattice=lat)
+    D, Q, shp = O.dims(d)
+    e, _ = O.lattice(lat)
+    xi = np.sqrt(3 * d["RT"]) * e[:, :D]
+    f = perturb(4, O.init(d, rho=np.full(shp, 1.01), u=np.full((D,) + shp, 0.02)), 2e-2)
+    fv = f.reshape(Q)
+    rho, u = fv.sum(), (xi * fv[:, None]).sum(0) / d["rho0"]
+    feq = O.feq(d, rho, np.concatenate([u, np.zeros(3 - D)]))[:Q]
+    r = (2 * tau - dt) / (2 * tau + dt)
+    fn = f
+    for n in range(1, 4):
+        fn = O.step(d, fn)
+        np.testing.assert_allclose(fn.reshape(Q) - feq, r ** n * (fv - feq), rtol=0, atol=5e-16 * n)
+
+
+@pytest.mark.parametrize("lat", [9, 19, 27])
 @pytest.mark.parametrize("stretch", [0, 1])
 def test_periodic_conservation_without_force(lat, stretch):
     if lat == 9:
