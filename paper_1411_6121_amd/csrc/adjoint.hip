@@ -29,6 +29,7 @@
 
 #include "ctx.hpp"
 #include "kernels_general.hpp"
+#include "march.hpp"
 
 namespace dugks {
 
@@ -367,7 +368,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ADJ_TX * ADJ_TY), amdgp
     __shared__ T dts[D][NS][NR];  // d_hat_t of the region's cells, velocities with e_t != 0
     const Inst<T>& P = *Pp;
     const long long stride = (long long)Q * P.nc;
-    const int x0 = (int)(blockIdx.x % tiles_x) * ADJ_TX, y0 = (int)(blockIdx.x / tiles_x) * ADJ_TY;
+    // tiles in XCD order: each XCD takes a contiguous range of tile rows, so
+    // tiles sharing halo lines read them through one L2
+    const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int x0 = (b % tiles_x) * ADJ_TX, y0 = (b / tiles_x) * ADJ_TY;
     const int tx = (int)threadIdx.x % ADJ_TX, ty = (int)threadIdx.x / ADJ_TX;
     const int rc = (ty + 1) * RX + (tx + 1);  // this thread's cell in the region
     // the thread's cell (the wrapped coordinates past a ragged mesh edge:
@@ -497,7 +501,10 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY) void k_adj_face_tile(
     constexpr int RX = ADJ_TX + 2, RY = ADJ_TY + 2, NR = RX * RY, NC = ADJ_TX * ADJ_TY;
     __shared__ T phs[Q * NR];
     const Inst<T>& P = *Pp;
-    const int x0 = (int)(blockIdx.x % tiles_x) * ADJ_TX, y0 = (int)(blockIdx.x / tiles_x) * ADJ_TY;
+    // tiles in XCD order: each XCD takes a contiguous range of tile rows, so
+    // tiles sharing halo lines read them through one L2
+    const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int x0 = (b % tiles_x) * ADJ_TX, y0 = (b / tiles_x) * ADJ_TY;
 #pragma unroll 1
     for (int r = (int)threadIdx.x; r < NR; r += NC) {
         const int cx = wrap_any(x0 - 1 + r % RX, P.n[0]), cy = wrap_any(y0 - 1 + r / RX, P.n[1]);

@@ -2,8 +2,10 @@
 benchmark times: the D3Q19 128^3 cavity (uniform and tanh meshes, FP64 and
 FP32), the D2Q9 1024^2 cavity, the 2-D Re = 12000 cavity (128^2 tanh
 mesh, bounce-back walls), the 4 x 32 channel over 20000 steps, the 32 x 256
-Womersley channel, the 64-instance uneven batch, and a 640^3 periodic mesh
-(5e9 state elements, past 32-bit offsets) checked block by block.
+Womersley channel, the 64-instance uneven batch, a 640^3 periodic mesh
+(5e9 state elements, past 32-bit offsets) checked block by block, the
+spanwise mirror symmetry of the GPU's own 128^3 cavity runs, and the
+pressure-driven Womersley channel of Sec. III.C at its printed parameters.
 
 Whole-field comparisons: one oracle step at these sizes takes well under a
 second on the host cores, so every output value is checked, not a sample.
