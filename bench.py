@@ -4,7 +4,7 @@
 Workload (headline): D3Q19 cubic lid-driven cavity, 128^3 cells, lid U = 0.1
 along x, NEQ velocity walls on all six sides, rho0 = 1, RT = 1/3, dx = 1,
 Re = 100 (tau = U N / (Re RT)), CFL 0.5, FP64, started from rest.  One
-"step" is one full time step (Appendix steps 1-9) over every cell and every
+"step" is one full time step (Sec. II.B) over every cell and every
 discrete velocity: one launch of the fused step kernel.  Prints one JSON
 line:
 

@@ -168,7 +168,7 @@ int dugks_reset(dugks_ctx* ctx, const void* rho, const void* u, const void* forc
                 void* f_out, void* stream);
 
 /*
- * One time step t_n -> t_n + dt of the Appendix algorithm (steps 1-9):
+ * One time step t_n -> t_n + dt of the scheme (Sec. II.B and the Appendix):
  * f-bar-plus at the centres (Eq. f_bar_+), ghost extrapolation, interface
  * reconstruction f-bar(x_b, t_n+h) = f-bar-plus(x_b) - xi h . grad
  * (Eq. gradient), wall rules (Eqs. BB, NEQ), interface moments, original
@@ -190,7 +190,7 @@ int dugks_run(dugks_ctx* ctx, void* f_a, void* f_b, const void* force, double t0
               void* stream, int* which_out);
 
 /*
- * Macroscopic fields at time t (Eq. macro_values; Appendix step 10):
+ * Macroscopic fields at time t (Eq. macro_values):
  *   rho = sum_q f~_q, u = sum_q xi_q f~_q / rho0 + dt/2 G(x, t),
  *   p = (rho - rho0) RT.  rho, u [D], p are nullable device outputs.
  * totals_host (nullable, 6 doubles, host memory): sum V rho, sum V j_x,
@@ -233,7 +233,7 @@ int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, cons
                           double t_b, double* out_host, void* stream);
 
 /*
- * Reverse mode of one step (Appendix steps 1-9 transposed, incompressible
+ * Reverse mode of one step (the scheme of Sec. II.B transposed, incompressible
  * model, D2Q9 and D3Q19) on any mesh and boundary set: periodic sides,
  * bounce-back (Eq. BB) and NEQ velocity/pressure walls (Eq. NEQ), uniform
  * or tanh-stretched axes:
@@ -244,7 +244,7 @@ int dugks_velocity_change(dugks_ctx* ctx, const void* f_a, const void* f_b, cons
  * (f-bar-plus and the interface adjoints; then the cell adjoints, the
  * neighbours' terms staged in LDS), in 3-D four passes; meshes with walls a
  * gather form over every face and the ghost-extended grid (the ghost rule
- * of step 2 is transposed).  The scratch (2-D periodic: D (Q + D) values per
+ * of the ghost values is transposed).  The scratch (2-D periodic: D (Q + D) values per
  * cell; otherwise about (2 + D) Q values per extended cell plus (Q + D) per
  * face and per cell) is allocated on first use and kept by the context.  lam_n must not alias f_n or lam_np1.  The original-model
  * variant and D3Q27 return DUGKS_EUNSUPPORTED.  Asynchronous.

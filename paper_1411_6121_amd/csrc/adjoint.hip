@@ -2,14 +2,14 @@
 // the initial state; gather form (no atomics), forward intermediates
 // recomputed from f_n (no tape).
 //
-// Forward, per interface b of axis a between cells L and R (step 4 written
+// Forward, per interface b of axis a between cells L and R (Eq. gradient written
 // through the cell quantities psi_a(c) = phi(c) - h sum_{t!=a} xi_t d_t(c),
 // d_t the cell-centred derivative d_t(c) = cp phi(c+t) + c0 phi(c) + cm phi(c-t)):
 //   fbar(b) = (1-w) psi_a(L) + w psi_a(R) - h xi_a g (phi(R) - phi(L)).
 // Reverse, with lam the adjoint of f_{n+1}:
 //   pass A (per cell R, axis a: its lower face b): recompute fbar(b), its
 //     moments and the original f(b); adjoint of the flux terms
-//     fhat_q = xi_{q,a} (dt/Delta(R) lam_q(R) - dt/Delta(L) lam_q(L)), of step 7
+//     fhat_q = xi_{q,a} (dt/Delta(R) lam_q(R) - dt/Delta(L) lam_q(L)), of Eq. (original_f)
 //     and of the moments -> fbar_hat(b) (all q) and G_hat(b);
 //   pass B (per cell): psi_hat_a from the two faces of each axis, the normal
 //     terms, d_hat_t = -h xi_t sum_{a!=t} psi_hat_a, and the local part of
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_adj_cell1(const Inst<T>* __restrict__ P
 }
 
 // reverse of Eq. (f_bar_+) at the cell and of the macroscopic recovery
-// (step 1), given the cell's complete phi-hat: lam_n = phi-hat terms - 1/3
+// (Eqs. macro_values, f_bar_+), given the cell's complete phi-hat: lam_n = phi-hat terms - 1/3
 // lam_{n+1} (Eq. f_tilde_+), and the force-field gradient (cell term at t_n,
 // face terms at t_n + h from the face adjoints ga)
 template <class LAT, typename T>
@@ -605,11 +605,11 @@ __global__ __launch_bounds__(256) void k_phi_adj(const Inst<T>* __restrict__ Pp,
 // periodic axis equals face 0 in the forward step and is transposed as a
 // face of its own), and the adjoint of f-bar-plus lives on the whole
 // ghost-extended grid; the ghost rule is transposed at the end.
-//   face pass   (per face): recompute F (steps 3-4) and the wall rule
-//                (step 5) at wall faces; reverse of the flux (adjacent
-//                interior cells only), of step 7 and of the face moments ->
-//                adjoint of F after step 5, and of the face acceleration;
-//                At wall faces the same thread transposes step 5 (bounce-back:
+//   face pass   (per face): recompute F (Eq. gradient) and the wall rule
+//                (Eqs. BB, NEQ) at wall faces; reverse of the flux (adjacent
+//                interior cells only), of Eq. (original_f) and of the face moments ->
+//                adjoint of F after the wall rule, and of the face acceleration;
+//                At wall faces the same thread transposes the wall rule (bounce-back:
 //                a permutation; NEQ: the replaced values depend on the values
 //                and moments of the opposite interface x_c of the wall cell,
 //                whose share is kept per line and side and added to x_c by
@@ -663,7 +663,7 @@ __device__ __forceinline__ long long line_of(const Inst<T>& P, int A, const int*
     return li;
 }
 
-// F after steps 3-4 on face c (c[A] = face index) of axis A, all velocities
+// F of Eq. (gradient) on face c (c[A] = face index) of axis A, all velocities
 template <class LAT, typename T, int A>
 __device__ __forceinline__ void face_recon_at(const Inst<T>& P, const T* __restrict__ phi, const int* c, T* out)
 {
@@ -752,7 +752,7 @@ __device__ __forceinline__ void adjw_face_body(const Inst<T>& P, long long fi, c
         vb[q] = v;
     }
     if (wlo || whi) {
-        // transpose of step 5: vb becomes the adjoint of the values before the
+        // transpose of the wall rule: vb becomes the adjoint of the values before the
         // rule; NEQ contributions to the opposite interface x_c go to the
         // line's slot of `ex`/`gx`, added to that face by the psi pass
         const int s = wlo ? 2 * A : 2 * A + 1;
@@ -1011,7 +1011,7 @@ __device__ __forceinline__ T phi_hat_q(const Inst<T>& P, const T* __restrict__ p
     return acc;
 }
 
-// the points of axis a whose value the ghost rule (step 2) builds from the
+// the points of axis a whose value the ghost rule builds from the
 // cell with coordinate x along a, with their weights: the cell itself and
 // up to two ghosts (wall: linear extrapolation; periodic: copies)
 template <typename T>
@@ -1037,7 +1037,7 @@ __device__ __forceinline__ int ghost_sources(const Inst<T>& P, int a, int x, int
 }
 
 // phi_hat of velocity q at an interior cell, gathered from the cell and every
-// ghost the ghost rule builds from it (transpose of step 2, tensor-product
+// ghost the ghost rule builds from it (transpose of the ghost rule, tensor-product
 // weights); the q = 0 threads gather the force adjoint likewise
 template <class LAT, typename T, int q>
 __device__ __forceinline__ void adjw_gather_q(const Inst<T>& P, long long cidx, const T* __restrict__ php,

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_init_one(const Inst<T>* __restrict__ Pp
     init_body<LAT, T, ORIG>(P, c, rho, u, force, gt, fout);
 }
 
-// macroscopic fields and per-block partial totals (Appendix step 10)
+// macroscopic fields and per-block partial totals (Eq. macro_values)
 template <class LAT, typename T, bool ORIG>
 __global__ __launch_bounds__(256) void k_moments_one(const Inst<T>* __restrict__ Pp, const T* __restrict__ f, const T* __restrict__ force,
                                                      T gt, T* rho_o, T* u_o, T* p_o, double* partial)

@@ -49,7 +49,7 @@ struct Inst {
     long long poff;// element offset of its f-bar-plus scratch (batched)
     T rho0, RT, c, h, dt;
     T B1, C1;      // Eq. (f_bar_+) in deviation form: phi = f + B1 (feq - f) + C1 S
-    T B7, C7;      // step 7:  f = fbar + B7 (feq - fbar) + C7 S
+    T B7, C7;      // Eq. (original_f) inverted: f = fbar + B7 (feq - fbar) + C7 S
     // update without the cell's own state (no acceleration):
     // f~(n+1) = phi + Bu (feq - phi) - fluxes, Bu = B1 / (3 (1 - B1)), from
     // Eq. (f_tilde_+) with f~ = (phi - B1 feq) / (1 - B1).  Bu has a pole at

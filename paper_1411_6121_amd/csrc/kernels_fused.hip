@@ -2,12 +2,13 @@
 //
 // One workgroup owns a halo-inclusive tile of columns in the plane of the
 // first D-1 axes (one thread per column) and marches along the last axis
-// (z in 3-D, y in 2-D) over a chunk of planes.  f-bar-plus (Appendix
-// steps 1-2) of three consecutive planes lives in an LDS ring; each new plane
-// is computed from the state once per column (ghost columns and ghost planes
-// by extrapolation inside LDS), and every interior thread then performs
-// steps 3-9 for its cell from LDS: the state is read once from HBM (plus the
-// tile halo, which hits L2) and the new state written once.
+// (z in 3-D, y in 2-D) over a chunk of planes.  f-bar-plus (Eq. f_bar_+,
+// with the ghost rule) of three consecutive planes lives in an LDS ring;
+// each new plane is computed from the state once per column (ghost columns
+// and ghost planes by extrapolation inside LDS), and every interior thread
+// then performs the interface and update stages for its cell from LDS: the
+// state is read once from HBM (plus the tile halo, which hits L2) and the new
+// state written once.
 //
 // Faces are evaluated by both neighbouring cells with identical code and
 // operands, so the two sides see bitwise-identical fluxes (conservation to
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(BX* BY, MINW) void k_fused(const Inst<T>* __restric
 // upper x (and y) interface (tile halo columns included) into an LDS face
 // buffer and each updating column its upper march-axis interface (kept in
 // registers for the next plane); after a barrier every updating cell takes
-// the differences of its two faces per axis (steps 8-9).
+// the differences of its two faces per axis (Eqs. microflux, f_tilde_+).
 // ---------------------------------------------------------------------------
 template <class LAT, typename T, int BX, int BY, bool PF, bool UNI>
 __device__ __forceinline__ void fused2_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,

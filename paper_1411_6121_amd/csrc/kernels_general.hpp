@@ -2,13 +2,13 @@
 // force), used for every configuration and as the batched path.
 //
 // Pass 1 (k_phi): f-bar-plus (Eq. f_bar_+) on every cell of the ghost-extended
-//   grid (Appendix steps 1-2); a ghost takes the linear extrapolation through
+//   grid (Eq. f_bar_+ and the ghost rule); a ghost takes the linear extrapolation through
 //   the two nearest centres of each wall axis (tensor product on edges and
 //   corners) or the wrapped cell of a periodic axis.
 // Pass 2 (k_update): per interior cell, both faces of every axis are
-//   reconstructed from pass 1 (steps 3-4), wall rules applied (step 5),
-//   interface moments and the original distribution formed (steps 6-7), and
-//   the conservative update written (steps 8-9).  Interior faces are thus
+//   reconstructed from pass 1 (Eq. gradient), wall rules applied (Eqs. BB, NEQ),
+//   interface moments and the original distribution formed (Eq. original_f), and
+//   the conservative update written (Eqs. microflux, f_tilde_+).  Interior faces are thus
 //   evaluated by both neighbours with the same code and operands, so the
 //   two sides see bitwise-identical fluxes and conservation holds to
 //   rounding.
@@ -31,7 +31,7 @@ __device__ __forceinline__ long long int_idx(const Inst<T>& P, int i, int j, int
     return ((long long)k * P.n[1] + j) * P.n[0] + i;
 }
 
-// f-bar-plus of one interior cell (Appendix step 1) from its state fv[Q]
+// f-bar-plus of one interior cell (Eq. f_bar_+) from its state fv[Q]
 // and its force-field values fg[D] (used if has_field)
 template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void phi_from(const Inst<T>& P, const T (&fv)[LAT::Q], const T (&fg)[3], bool has_field,
@@ -204,7 +204,7 @@ __device__ __forceinline__ CellMetric<T> load_metric(const Inst<T>& P, int a, in
     return CellMetric<T>{m.w[i], m.w[i + 1], m.gn[i], m.gn[i + 1], m.cp[i], m.c0[i], m.cm[i], m.fdx[i]};
 }
 
-// interface moments (Appendix step 6): rho, u = j/rho0 + h/2 G
+// interface moments (Eq. macro_values at the interface): rho, u = j/rho0 + h/2 G
 template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void face_moments(const Inst<T>& P, const T* fb, const T* G, T& rho, T* u)
 {
@@ -247,7 +247,7 @@ __device__ __forceinline__ void neq_capture(const Inst<T>& P, int a, const T* op
     }
 }
 
-// Appendix step 5 on a wall face of side s (Eqs. BB, NEQ), in place on the
+// the wall rules of Eqs. (BB), (NEQ) on a wall face of side s, in place on the
 // reconstructed values, for the velocities entering the domain.
 template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, const NeqInfo<LAT, T>& I, T gth)
@@ -285,7 +285,7 @@ __device__ __forceinline__ void wall_rule(const Inst<T>& P, int s, T* wall, cons
     }
 }
 
-// Appendix step 7 for the velocities that cross a face of axis a
+// the inverse of Eq. (original_f) for the velocities that cross a face of axis a
 template <class LAT, typename T, bool ORIG = false>
 __device__ __forceinline__ void face_original(const Inst<T>& P, int a, T* fb, const T* G)
 {
@@ -301,7 +301,7 @@ __device__ __forceinline__ void face_original(const Inst<T>& P, int a, T* fb, co
     }
 }
 
-// Appendix steps 3-4, compile-time axis A, run-time side (see recon_face)
+// Eq. (gradient), compile-time axis A, run-time side (see recon_face)
 template <class LAT, typename T, class ACC, int A>
 __device__ __forceinline__ void recon_face_ct(const Inst<T>& P, const ACC& ph, bool upper, const CellMetric<T>& ma,
                                               const CellMetric<T>& mx, const CellMetric<T>& my,
@@ -369,7 +369,7 @@ __device__ __forceinline__ void axis_fluxes_ct(const Inst<T>& P, const ACC& ph, 
 // ---------------------------------------------------------------------------
 // faces evaluated once (fused kernel v2): the value of the interface of axis
 // A with index f between the cells at offsets off and off+1 (relative to the
-// thread's cell), after steps 3-7; walls handled in place.
+// thread's cell), after reconstruction, wall rules and Eq. (original_f); walls handled in place.
 // ---------------------------------------------------------------------------
 
 // index of velocity q among the velocities crossing a face of axis A
@@ -424,7 +424,7 @@ __device__ __forceinline__ void recon_at(const Inst<T>& P, const ACC& ph, int of
 
 // ci: global cell coordinates of the thread's cell (tangential ones are
 // used for metrics and force); f: face index along A.  out[cross_slot]
-// receives f_q (step 7) for the velocities crossing the face.
+// receives f_q (Eq. original_f inverted) for the velocities crossing the face.
 template <class LAT, typename T, class ACC, int A, bool UNI>
 __device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const int* ci,
                                           int off, int f, T gth, const CellMetric<T>& mx, const CellMetric<T>& my,
@@ -459,7 +459,7 @@ __device__ __forceinline__ void face_once(const Inst<T>& P, const ACC& ph, const
         if (LAT::e(q, A) != 0) out[cross_slot<LAT, A>(q)] = fb[q];
 }
 
-// Steps 3-9 for one cell: acc holds f~+ on entry (Eq. f_tilde_+) and the
+// The interface and update stages for one cell: acc holds f~+ on entry (Eq. f_tilde_+) and the
 // updated state on exit.  Faces are taken one at a time; on a wall axis the
 // opposite (interior) face is evaluated first so that the NEQ rule can use
 // its moments and non-equilibrium part.

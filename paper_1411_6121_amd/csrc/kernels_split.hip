@@ -91,7 +91,7 @@ struct HalfPhi {
     __device__ __forceinline__ T rest(int b) const { return s[b + LAT::REST * SQ]; }
 };
 
-// cell moments and f-bar-plus (Appendix step 1, Eq. f_bar_+) of the lane's
+// cell moments and f-bar-plus (Eqs. macro_values, f_bar_+) of the lane's
 // velocities; fv: lane velocities, fr: rest velocity (both lanes hold it)
 template <class LAT, typename T, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::REST], T fr, const T (&fg)[3],
@@ -146,7 +146,7 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
     }
 }
 
-// Appendix steps 3-4 for the lane's velocities on the interface of axis A
+// Eq. (gradient) for the lane's velocities on the interface of axis A
 // between the cells at offsets off and off+1 (weight w of the right cell,
 // normal-difference scale gn); the rest velocity (no gradient term) too
 template <class LAT, typename T, class ACC, int A, bool UNI>
@@ -188,7 +188,7 @@ __device__ __forceinline__ void recon_half(const Inst<T>& P, const ACC& ph, int 
     else orest = rL + w * (rR - rL);
 }
 
-// interface moments (Appendix step 6) from the two lanes' values
+// interface moments (Eq. macro_values at the interface) from the two lanes' values
 template <class LAT, typename T, bool NOG = false, bool ORIG = false>
 __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
                                              T& rho, T* u)
@@ -240,7 +240,7 @@ __device__ __forceinline__ void neq_capture_half(const Inst<T>& P, const T (&fb)
     }
 }
 
-// Appendix step 5 on a wall face of side s = 2A + (sgs > 0) (Eqs. BB, NEQ)
+// the wall rules of Eqs. (BB), (NEQ) on a wall face of side s = 2A + (sgs > 0)
 // for the lane's velocities entering the domain (sigma e_A sgs < 0)
 template <class LAT, typename T, int A, bool ORIG = false>
 __device__ __forceinline__ void wall_half(const Inst<T>& P, int s, int sgs, T (&wall)[LAT::REST],
@@ -312,8 +312,10 @@ __device__ __forceinline__ void face_force_ring(const Inst<T>& P, const GV& gv, 
 }
 
 // The interface of axis A with index f between the cells at offsets off and
-// off+1: steps 3-7 for the lane's velocities; out[half_cross_slot] receives
-// f (step 7) of the lane's velocities crossing the face.
+// off+1: reconstruction (Eq. gradient), wall rules, interface moments and the
+// original distribution (the inverse of Eq. original_f) for the lane's
+// velocities; out[half_cross_slot] receives f of the lane's velocities
+// crossing the face.
 // NW: the caller knows that the face is no wall face (the wall code is
 // compiled out)
 template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false, bool NW = false,
@@ -363,10 +365,10 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
         if (LAT::e(k, A) == 0) continue;
         const T fe = feq_pt<LAT, T, ORIG>(P, E, k);
         if constexpr (NOG) {
-            out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]);  // step 7 without a source
+            out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]);  // inverse of Eq. (original_f) without a source
         } else {
             const T S = srcf_pt<LAT, T>(P, E, k) * fe;
-            out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]) + P.C7 * S;  // step 7
+            out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]) + P.C7 * S;  // inverse of Eq. (original_f)
         }
     }
 }
