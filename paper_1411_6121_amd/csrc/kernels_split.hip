@@ -944,9 +944,12 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
 int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk)
 {
     if (ctx->cfg.lattice == DUGKS_D3Q27) {
-        // 27 velocities: an 18 x 9 column tile keeps the LDS ring within a CU
+        // 27 velocities: one tile's LDS ring fills a CU.  FP64 takes a 16 x 8
+        // tile, four waves (one per SIMD), whose state fits the register file
+        // without scratch; an 18 x 9 tile (six waves) would spill to scratch.
+        // FP32 keeps 18 x 9, two waves per SIMD without spills.
         if (ctx->cfg.dtype == DUGKS_F64)
-            return launch_split<D3Q27, double, 18, 9, 1, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
+            return launch_split<D3Q27, double, 16, 8, 1, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
         return launch_split<D3Q27, float, 18, 9, 2, false>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
     }
     if (ctx->cfg.lattice == DUGKS_D3Q19) {
