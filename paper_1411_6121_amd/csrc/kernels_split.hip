@@ -47,6 +47,27 @@ __device__ __forceinline__ double partner(double v)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// value of lane l + N (N > 0) or l - N (N < 0) of the lane's 16-lane row
+// (DPP row shift; a source outside the row leaves an unspecified value)
+template <int N>
+__device__ __forceinline__ unsigned row_shift_u32(unsigned v)
+{
+    constexpr int ctrl = N > 0 ? 0x100 + N : 0x110 - N;  // row_shl:N / row_shr:-N
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ float row_shift(float v)
+{
+    return __uint_as_float(row_shift_u32<N>(__float_as_uint(v)));
+}
+template <int N>
+__device__ __forceinline__ double row_shift(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = row_shift_u32<N>((unsigned)b), hi = row_shift_u32<N>((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // number of half-0 velocities crossing a face of axis A, and the slot of k
 template <class LAT, int A>
 __host__ __device__ constexpr int half_cross_slot(int k)
@@ -412,8 +433,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // and f-tilde(n+1) = phi + B1 / (3 (1 - B1)) (feq - phi) - fluxes.  FP32
     // D3Q19 (4 waves per SIMD, 128 registers) spends the freed own-state
     // registers on the late prefetch; D3Q27, which keeps no own state in
-    // registers, saves the second read of it (FP32 also takes the prefetch,
-    // FP64 has no registers for it).  The host launches these instances only
+    // registers, saves the second read of it (and takes the late prefetch
+    // in both precisions).  The host launches these instances only
     // where |1 - B1| >= 1/4 (Inst::bu_ok); elsewhere it takes the instance
     // with the acceleration terms, whose skipped terms are exact zeros.
     constexpr bool PHIU = NOG && !ORIG && LPF && ((LAT::Q == 19 && sizeof(T) == 4) || LAT::Q == 27);
@@ -459,6 +480,15 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                        g[1] <= P.n[1] - 1;
 
     const bool any_ghost = NW ? false : __syncthreads_or(ghost_col) != 0;
+    // XSH (3-D tiles 16 columns wide, whose rows are the 16-lane segments of
+    // a wave): in a tile whose only ghost columns are those of the x walls,
+    // a ghost column extrapolates f-bar-plus from the two cells beside it in
+    // its row, taken from their lanes by a shuffle (wave-local, before the
+    // plane's barrier) instead of from LDS after a second barrier
+    constexpr bool XSH = !NW && D == 3 && BX == 16;
+    const bool xsh_tile = XSH && any_ghost && __syncthreads_or(ghost_col && kind[1] != COL_CELL) == 0;
+    const bool xg_lo = xsh_tile && !P.per[0] && b0 == 0;
+    const bool xg_hi = xsh_tile && !P.per[0] && b0 * (BX - 2) - 1 + (BX - 1) >= P.n[0];
     const bool gr_on = (D == 2) && force != nullptr;
     auto gslot = [&](int p, int d) { return (ring(p) * D + d) * SQ + ty * BX + tx; };
     const int nM = P.n[M];
@@ -513,8 +543,10 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     // wait and the update instead of stalling the next f-bar-plus stage (2 %
     // at 128^3; the batched and force-field instances, and FP32 with the
     // own-state ring, run out of registers with it: D2Q9 512^2 with a field
-    // 30 -> 39 us; FP32 takes it with PHIU, D3Q27 FP64 does not).
-    constexpr bool LP = LPF && ((OWNR && sizeof(T) == 8) || (PHIU && (LAT::Q == 19 || sizeof(T) == 4)));
+    // 30 -> 39 us).  PHIU launches take it too: FP32 D3Q19 in the registers
+    // the own state frees, D3Q27 in both precisions (FP64 D3Q27 runs one
+    // wave per SIMD, whose register file has room for it: 3 % at 128^3).
+    constexpr bool LP = LPF && ((OWNR && sizeof(T) == 8) || PHIU);
     T pn[K], pnr = T(0), pgn[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < K; ++k) pn[k] = T(0);
@@ -543,8 +575,8 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         for (int a = 0; a < 3; ++a) pg[a] = pgn[a];
     };
     auto compute_plane = [&](int p) {
+        T v[K], vr;
         if (cell_col) {
-            T v[K], vr;
             phi_half<LAT, T, NOG, ORIG>(P, pf, prest, pg, force != nullptr, gt, sg, v, vr);
 #pragma unroll
             for (int k = 0; k < K; ++k) lds[lds_el(p, hs + k, 0, 0)] = v[k];
@@ -554,8 +586,29 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                 for (int d = 0; d < D; ++d) gring[gslot(p, d)] = pg[d];
             }
         }
+        if constexpr (XSH) {
+            // the ghost rule (linear extrapolation through the two nearest
+            // centres) with the centres' values from lanes +1, +2 (low wall) or
+            // -1, -2 (high wall) of the row; every lane of the wave takes part
+            auto ghost_x = [&](bool lo, int kindg, T r) {
+#pragma unroll
+                for (int k = 0; k <= K; ++k) {
+                    const T x = k < K ? v[k] : vr;
+                    const T s1 = lo ? row_shift<1>(x) : row_shift<-1>(x);
+                    const T s2 = lo ? row_shift<2>(x) : row_shift<-2>(x);
+                    T acc = (T(1) - r) * s1;
+                    acc += r * s2;
+                    if (ghost_col && kind[0] == kindg) {
+                        if (k < K) lds[lds_el(p, hs + k, 0, 0)] = acc;
+                        else if (h == 0) lds[lds_el(p, K, 0, 0)] = acc;
+                    }
+                }
+            };
+            if (xg_lo) ghost_x(true, COL_GHOST_LO, P.rlo[0]);
+            if (xg_hi) ghost_x(false, COL_GHOST_HI, P.rhi[0]);
+        }
         __syncthreads();
-        if (!any_ghost) return;
+        if (!any_ghost || xsh_tile) return;
         if (ghost_col) {
             int off[2][2];
             T wt[2][2];
