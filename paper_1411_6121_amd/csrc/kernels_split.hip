@@ -339,17 +339,90 @@ __device__ __forceinline__ void face_force_ring(const Inst<T>& P, const GV& gv, 
 // crossing the face.
 // NW: the caller knows that the face is no wall face (the wall code is
 // compiled out)
+// RX (x faces of tiles whose rows are 16-lane segments): the NEQ rule's
+// values at the opposite interface of a wall cell (interface moments and
+// non-equilibrium part) are those of the face that the next lane of the row
+// (low wall) or the previous one (high wall) evaluates in the same call; the
+// wall face takes them from that lane (DPP row shift) instead of
+// reconstructing the interface again.  rxw: the tile has the low (1) and / or
+// high (2) wall face of the axis (uniform over the workgroup).
 template <class LAT, typename T, class ACC, int A, bool UNI, bool NOG = false, bool ORIG = false, bool NW = false,
-          class GV>
+          bool RX = false, class GV>
 __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const T* __restrict__ force, const GV& gv,
                                           const int* ci, int off, int f, T gth, const CellMetric<T>& mx,
-                                          const CellMetric<T>& my, const CellMetric<T>& mz, T sg, int sgi, T* out)
+                                          const CellMetric<T>& my, const CellMetric<T>& mz, T sg, int sgi, T* out,
+                                          int rxw = 0)
 {
     constexpr int K = LAT::REST;
     const AxisMetric<T>& m = P.m[A];
     const int n = P.n[A];
     const bool wall_lo = !NW && !P.per[A] && f == 0;
     const bool wall_hi = !NW && !P.per[A] && f == n;
+    if constexpr (RX) {
+        static_assert(A == 0 && !NW, "row exchange: x faces of the wall body");
+        T fb[K], fr, G[3];
+        const T w = UNI ? T(0.5) : m.w[f];
+        recon_half<LAT, T, ACC, A, UNI>(P, ph, off, w, UNI ? P.ugn[A] : m.gn[f], mx, my, mz, sg, fb, fr);
+        if constexpr (NOG) G[0] = G[1] = G[2] = T(0);
+        else face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
+        T rho, u[3];
+        moments_half<LAT, T, NOG, ORIG>(P, fb, fr, G, sg, rho, u);
+        T us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int a = 0; a < LAT::D; ++a) {
+            us[a] = sg * u[a];
+            Gs[a] = sg * G[a];
+        }
+        EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
+        T fe[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (LAT::e(k, A) != 0) fe[k] = feq_pt<LAT, T, ORIG>(P, E, k);
+        if (rxw) {
+            // every lane of the call takes part in the shifts
+            auto take = [&](T x) -> T {
+                T r = x;
+                if (rxw & 1) {
+                    const T sx = row_shift<1>(x);
+                    if (wall_lo) r = sx;
+                }
+                if (rxw & 2) {
+                    const T sx = row_shift<-1>(x);
+                    if (wall_hi) r = sx;
+                }
+                return r;
+            };
+            NeqHalf<LAT, T> info;
+            info.rc = take(rho);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) info.uc[a] = a < LAT::D ? take(u[a]) : T(0);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (LAT::e(k, A) != 0) info.neq[k] = take(fb[k] - fe[k]);
+            if (wall_lo || wall_hi) {
+                if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi, gth);
+                if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi, gth);
+                moments_half<LAT, T, NOG, ORIG>(P, fb, fr, G, sg, rho, u);
+#pragma unroll
+                for (int a = 0; a < LAT::D; ++a) us[a] = sg * u[a];
+                E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (LAT::e(k, A) != 0) fe[k] = feq_pt<LAT, T, ORIG>(P, E, k);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (LAT::e(k, A) == 0) continue;
+            if constexpr (NOG) {
+                out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe[k] - fb[k]);
+            } else {
+                const T S = srcf_pt<LAT, T>(P, E, k) * fe[k];
+                out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe[k] - fb[k]) + P.C7 * S;
+            }
+        }
+        return;
+    }
     NeqHalf<LAT, T> info;
     asm volatile("" ::: "memory");
     T fb[K], fr, G[3];
@@ -489,6 +562,13 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     const bool xsh_tile = XSH && any_ghost && __syncthreads_or(ghost_col && kind[1] != COL_CELL) == 0;
     const bool xg_lo = xsh_tile && !P.per[0] && b0 == 0;
     const bool xg_hi = xsh_tile && !P.per[0] && b0 * (BX - 2) - 1 + (BX - 1) >= P.n[0];
+    // the tile's x wall faces, for the row exchange of the x-face stage
+    // (D3Q27, whose one wave per SIMD has registers to spare; in D3Q19 FP64,
+    // at 256 registers, the second pass spills what the exchange saves)
+    constexpr bool RX = XSH && LAT::Q == 27;
+    const int rxw = RX ? ((!P.per[0] && b0 == 0) ? 1 : 0) |
+                              ((!P.per[0] && b0 * (BX - 2) - 1 + (BX - 1) >= P.n[0]) ? 2 : 0)
+                        : 0;
     const bool gr_on = (D == 2) && force != nullptr;
     auto gslot = [&](int p, int d) { return (ring(p) * D + d) * SQ + ty * BX + tx; };
     const int nM = P.n[M];
@@ -758,7 +838,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
         T zhi[NM > 0 ? NM : 1];
         if (xface) {
             T v[NX];
-            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v);
+            if constexpr (D == 3) face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG, NW, RX>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmy, cmm, sg, sgi, v, rxw);
             else face_half<LAT, T, HalfPhi<LAT, T, BX, BY>, 0, UNI, NOG, ORIG, NW>(P, ph, force, gview(z), ci, 0, g[0] + 1, gth, cmx, cmm, cmm, sg, sgi, v);
 #pragma unroll
             for (int kc = 0; kc < NX; ++kc) fxb[((h * NX + kc) * BY + ty) * BX + tx] = v[kc];
