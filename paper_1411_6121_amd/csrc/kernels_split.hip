@@ -488,8 +488,8 @@ constexpr bool own_regs()
 // NW: the workgroup's tile and chunk touch no wall (no wall faces, ghost
 // columns or ghost planes); that code is then compiled out of the body that
 // most workgroups of a large mesh run.  Used for D3Q19 launches of instances
-// without acceleration (elsewhere the second body costs spilled registers:
-// FP32 with acceleration, D3Q27)
+// without acceleration (elsewhere the second body costs spilled registers,
+// FP32 with acceleration, or gains nothing measurable: D3Q27)
 template <class LAT, typename T, int BX, int BY, bool PF, bool UNI, bool OWN, bool NOG = false, bool ORIG = false,
           bool LPF = false, bool NW = false>
 __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict__ fin, const T* __restrict__ force,
