@@ -1077,13 +1077,15 @@ static int launch_split(dugks_ctx* ctx, const Inst<T>& P, const void* fin, void*
 int split_step(dugks_ctx* ctx, const void* fin, void* fout, const void* force, double t, hipStream_t st, int chunk)
 {
     if (ctx->cfg.lattice == DUGKS_D3Q27) {
-        // 27 velocities: one tile's LDS ring fills a CU.  FP64 takes a 16 x 8
-        // tile, four waves (one per SIMD), whose state fits the register file
-        // without scratch; an 18 x 9 tile (six waves) would spill to scratch.
-        // FP32 keeps 18 x 9, two waves per SIMD without spills.
+        // 27 velocities, 16 x 8 column tiles.  FP64: the tile's LDS ring
+        // (120 KB) fills a CU, four waves (one per SIMD) whose state fits the
+        // register file without scratch; an 18 x 9 tile (six waves) would
+        // spill to scratch.  FP32: 60 KB, so two workgroups (eight waves)
+        // share a CU, where an 18 x 9 tile (76 KB, six waves at over 170
+        // registers) leaves one.
         if (ctx->cfg.dtype == DUGKS_F64)
             return launch_split<D3Q27, double, 16, 8, 1, false>(ctx, ctx->pd, fin, fout, force, t, st, chunk);
-        return launch_split<D3Q27, float, 18, 9, 2, false>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
+        return launch_split<D3Q27, float, 16, 8, 2, false>(ctx, ctx->pf, fin, fout, force, t, st, chunk);
     }
     if (ctx->cfg.lattice == DUGKS_D3Q19) {
         // FP64: a 16 x 8 column tile (78 KB of LDS) lets two workgroups share
