@@ -18,6 +18,10 @@ def say(msg):
     print(msg, flush=True)
 
 
+# tangential velocities of the x walls (and the lid)
+XBB = [[0, 0.02, 0], [0, 0, -0.01], [0, 0, 0], [0.1, 0, 0], [0, 0, 0], [0, 0, 0]]
+
+
 def q27(name, n, bc, **kw):
     d = c3(name, n, bc, **kw)
     d["lattice"] = 27
@@ -35,6 +39,14 @@ CASES = [
     q27("d3q27-minimal", (2, 2, 2), (1, 1, 3, 3, 1, 1), uw=LID3),
     q27("d3q27-one-plane-periodic-z", (7, 6, 1), (1, 1, 1, 1, 0, 0), uw=LID3),
     q27("d3q27-one-column-periodic-x", (1, 5, 4), (0, 0, 3, 3, 1, 1), uw=LID3, G=(1e-4, 0, 0)),
+    # x walls of every kind (the x ghost columns and the x wall faces' NEQ
+    # values come from neighbouring lanes of the tile row): moving
+    # bounce-back walls on two x tiles, bounce-back / pressure in one tile,
+    # with acceleration, and a high ghost in the tile's last column (n = 14)
+    q27("d3q27-xwalls-bb-moving", (18, 9, 7), (3, 3, 1, 1, 0, 0), uw=XBB),
+    q27("d3q27-xwalls-mixed-kinds", (12, 10, 9), (3, 2, 1, 3, 1, 1), pw=[0, 1.5e-3, 0, 0, 0, 0], uw=LID3),
+    q27("d3q27-xwalls-accel", (16, 8, 6), (1, 1, 3, 3, 0, 0), uw=XBB, G=(0, 1e-4, 2e-4)),
+    q27("d3q27-xwalls-full-tile", (14, 7, 5), (1, 1, 1, 1, 3, 3), uw=LID3),
 ]
 
 
@@ -86,4 +98,25 @@ def test_d3q27_f32_velocity():
     got = gpu_run(dict(cfg, dtype="f32"), f0, 300)
     _, u_ref, _, _ = O.moments(cfg, ref)
     _, u_got, _, _ = O.moments(cfg, got)
+    assert np.abs(u_got - u_ref).max() / 0.1 < 2e-5
+
+
+F32_XWALLS = [
+    q27("q27f32-xwalls-bb-moving", (18, 9, 7), (3, 3, 1, 1, 0, 0), uw=XBB, tau=0.2),
+    q27("q27f32-xwalls-mixed-kinds", (12, 10, 9), (3, 2, 1, 3, 1, 1), pw=[0, 1.5e-3, 0, 0, 0, 0], uw=LID3, tau=0.2),
+]
+
+
+@pytest.mark.parametrize("cfg", F32_XWALLS, ids=[c["name"] for c in F32_XWALLS])
+def test_d3q27_f32_velocity_x_walls(cfg):
+    # the FP32 instance (16 x 8 tiles, two workgroups per CU) with x walls of
+    # each kind against the FP64 oracle over 300 steps: velocity within 2e-5
+    # of the lid speed U = 0.1
+    say(f"[d3q27 f32] {cfg['name']} n={cfg['n']}")
+    f0 = O.init(cfg)
+    ref = O.run(cfg, f0, 300)
+    got = gpu_run(dict(cfg, dtype="f32"), f0, 300)
+    _, u_ref, _, _ = O.moments(cfg, ref)
+    _, u_got, _, _ = O.moments(cfg, got)
+    assert np.abs(u_ref).max() > 0.005
     assert np.abs(u_got - u_ref).max() / 0.1 < 2e-5

@@ -159,6 +159,12 @@ CASES = [
     # holds the same plane three times), a tile axis of one column (both
     # halo columns are the cell itself), two cells on two periodic axes
     c3("d3q19-one-plane-periodic-z", (9, 7, 1), (1, 1, 1, 1, 0, 0), uw=LID3),
+    # x walls whose ghost columns come from neighbouring lanes of the tile
+    # row, without acceleration: moving bounce-back walls over two x tiles,
+    # and bounce-back / pressure in one tile
+    c3("d3q19-xwalls-bb-moving", (18, 9, 7), (3, 3, 1, 1, 0, 0),
+       uw=[[0, 0.02, 0], [0, 0, -0.01], [0, 0, 0], [0.1, 0, 0], [0, 0, 0], [0, 0, 0]]),
+    c3("d3q19-xwalls-mixed-kinds", (12, 10, 9), (3, 2, 1, 3, 1, 1), pw=[0, 1.5e-3, 0, 0, 0, 0], uw=LID3),
     c3("d3q19-one-column-periodic-x", (1, 6, 5), (0, 0, 3, 3, 1, 1), uw=LID3, G=(1e-4, 0, 0)),
     c3("d3q19-two-cell-periodic-yz", (5, 2, 2), (1, 1, 0, 0, 0, 0),
        uw=[[0, 0.01, 0], [0, 0, 0.01]] + [[0, 0, 0]] * 4),
