@@ -374,10 +374,6 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
             Gs[a] = sg * G[a];
         }
         EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
-        T fe[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (LAT::e(k, A) != 0) fe[k] = feq_pt<LAT, T, ORIG>(P, E, k);
         if (rxw) {
             // every lane of the call takes part in the shifts
             auto take = [&](T x) -> T {
@@ -398,7 +394,7 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
             for (int a = 0; a < 3; ++a) info.uc[a] = a < LAT::D ? take(u[a]) : T(0);
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (LAT::e(k, A) != 0) info.neq[k] = take(fb[k] - fe[k]);
+                if (LAT::e(k, A) != 0) info.neq[k] = take(fb[k] - feq_pt<LAT, T, ORIG>(P, E, k));
             if (wall_lo || wall_hi) {
                 if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi, gth);
                 if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi, gth);
@@ -406,19 +402,19 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
 #pragma unroll
                 for (int a = 0; a < LAT::D; ++a) us[a] = sg * u[a];
                 E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (LAT::e(k, A) != 0) fe[k] = feq_pt<LAT, T, ORIG>(P, E, k);
             }
         }
+        // feq again from the (wall lanes: updated) interface moments rather
+        // than held across the exchange (fewer live registers)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (LAT::e(k, A) == 0) continue;
+            const T fe = feq_pt<LAT, T, ORIG>(P, E, k);
             if constexpr (NOG) {
-                out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe[k] - fb[k]);
+                out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]);
             } else {
-                const T S = srcf_pt<LAT, T>(P, E, k) * fe[k];
-                out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe[k] - fb[k]) + P.C7 * S;
+                const T S = srcf_pt<LAT, T>(P, E, k) * fe;
+                out[half_cross_slot<LAT, A>(k)] = fb[k] + P.B7 * (fe - fb[k]) + P.C7 * S;
             }
         }
         return;
@@ -564,7 +560,7 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
     const bool xg_hi = xsh_tile && !P.per[0] && b0 * (BX - 2) - 1 + (BX - 1) >= P.n[0];
     // the tile's x wall faces, for the row exchange of the x-face stage
     // (D3Q27, whose one wave per SIMD has registers to spare; in D3Q19 FP64,
-    // at 256 registers, the second pass spills what the exchange saves)
+    // at 256 registers, the second pass spills about what the exchange saves)
     constexpr bool RX = XSH && LAT::Q == 27;
     const int rxw = RX ? ((!P.per[0] && b0 == 0) ? 1 : 0) |
                               ((!P.per[0] && b0 * (BX - 2) - 1 + (BX - 1) >= P.n[0]) ? 2 : 0)
