@@ -374,6 +374,36 @@ def cavity12000_cfg(n, dtype="f64"):
     return d
 
 
+def bench_wall_subsets(args):
+    """ms per step of the timed cavity (same mesh, lattice, precision and
+    time step) with walls on all axes, on none, and on each axis or pair
+    alone, the other axes periodic; the wall kinds stay those of the cavity
+    (NEQ, lid on the +y side)"""
+    import torch
+
+    import paper_1411_6121_amd as M
+
+    subsets = {"all": "xyz", "none": "", "x": "x", "y": "y", "z": "z", "xy": "xy"}
+    out = {}
+    for name, axes in subsets.items():
+        cfg = cavity_cfg(args.n, args.dtype, args.mesh, args.re, lattice=args.lattice)
+        cfg["bc"] = tuple(1 if "xyz"[a // 2] in axes else 0 for a in range(6))
+        Q, D, shp = M.shape_of(cfg)
+        f = torch.empty((Q,) + shp, dtype=M.torch_dtype(cfg), device="cuda")
+        g = torch.empty_like(f)
+        ctx = M.dugks_init(cfg, f)
+        try:
+            ms, cur = time_steps(ctx, cfg, f, g, args.steps, args.warmup)
+            M.dugks_moments(ctx, cur)  # the state stays finite
+        finally:
+            M.dugks_destroy(ctx)
+        del f, g, cur
+        out[name] = round(ms, 5)
+        print(f"walls on {name or 'none'}: {ms:.4f} ms", file=sys.stderr, flush=True)
+    return {"workload": workload_name(args.n, args.mesh, args.re, args.dtype, args.lattice),
+            "ms_per_step_by_wall_axes": out, "steps": args.steps, "warmup": args.warmup}
+
+
 def main_frequency(t, ek):
     """frequency of the largest spectral peak of E_k(t) above 0.05 (E_k
     detrended by a quadratic fit, Hann window), and the resolution 1/T"""
@@ -483,6 +513,9 @@ def main():
                          "about six minutes) and print its JSON line instead of the benchmark")
     ap.add_argument("--re12000-sizes", type=int, nargs="+", default=[128, 96, 80],
                     help="meshes of the Re = 12000 run")
+    ap.add_argument("--wall-subsets", action="store_true",
+                    help="time the timed cavity's step with walls on subsets of the axes (the others "
+                         "periodic) and print one JSON line: what the walls cost")
     args = ap.parse_args()
 
     workload = workload_name(args.n, args.mesh, args.re, args.dtype, args.lattice)
@@ -502,6 +535,9 @@ def main():
     torch.cuda.init()
     if args.cavity_re12000:
         print(json.dumps(bench_cavity12000(tuple(args.re12000_sizes))))
+        return
+    if args.wall_subsets:
+        print(json.dumps(bench_wall_subsets(args)))
         return
     if args.profile_case == "adjoint1024":
         print(json.dumps({"adjoint_1024": bench_adjoint(1024, steps=args.steps, warmup=args.warmup,
