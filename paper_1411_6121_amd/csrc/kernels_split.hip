@@ -47,6 +47,57 @@ __device__ __forceinline__ double partner(double v)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Lane-pair sums of two values at once: v_permlane32_swap(a, b) leaves
+// (a(l), b(l-32)) in its first result and (a(l+32), b(l)) in its second, so
+// one add gives the pair sum of a in the lower half-wave and that of b in
+// the upper one; a second swap of that sum with a copy of itself hands both
+// halves to every lane.  Each sum is the lower lane's value plus the upper
+// one's, bitwise what both lanes get from v + partner(v).  The copy is made
+// opaque to the compiler so that the swap never sees two equal operands.
+__device__ __forceinline__ void pair_sum2_u32(unsigned a, unsigned b, unsigned& r0, unsigned& r1)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    r0 = r[0];
+    r1 = r[1];
+}
+__device__ __forceinline__ void pair_sum2(float a, float b, float& sa, float& sb)
+{
+    unsigned x0, x1;
+    pair_sum2_u32(__float_as_uint(a), __float_as_uint(b), x0, x1);
+    const float sum = __uint_as_float(x0) + __uint_as_float(x1);
+    unsigned c = __float_as_uint(sum);
+    asm volatile("" : "+v"(c));
+    unsigned y0, y1;
+    pair_sum2_u32(__float_as_uint(sum), c, y0, y1);
+    sa = __uint_as_float(y0);
+    sb = __uint_as_float(y1);
+}
+__device__ __forceinline__ void pair_sum2(double a, double b, double& sa, double& sb)
+{
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    unsigned l0, l1, h0, h1;
+    pair_sum2_u32((unsigned)ua, (unsigned)ub, l0, l1);
+    pair_sum2_u32((unsigned)(ua >> 32), (unsigned)(ub >> 32), h0, h1);
+    const double sum = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0)) +
+                       __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+    const unsigned long long us = (unsigned long long)__double_as_longlong(sum);
+    unsigned clo = (unsigned)us, chi = (unsigned)(us >> 32);
+    asm volatile("" : "+v"(clo), "+v"(chi));
+    pair_sum2_u32((unsigned)us, clo, l0, l1);
+    pair_sum2_u32((unsigned)(us >> 32), chi, h0, h1);
+    sa = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0));
+    sb = __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+}
+// s[i] = x[i] + x[i] of the partner lane (the same column's other half)
+template <int N, typename T>
+__device__ __forceinline__ void pair_sums(const T (&x)[N], T (&s)[N])
+{
+#pragma unroll
+    for (int i = 0; i + 1 < N; i += 2) pair_sum2(x[i], x[i + 1], s[i], s[i + 1]);
+    if constexpr (N % 2 == 1) s[N - 1] = x[N - 1] + partner(x[N - 1]);
+}
+
 // value of lane l + N (N > 0) or l - N (N < 0) of the lane's 16-lane row
 // (DPP row shift; a source outside the row leaves an unspecified value)
 template <int N>
@@ -129,14 +180,18 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
             if (LAT::e(k, a) == -1) sj[a] -= fv[k];
         }
     }
-    const T rho = (rh + partner(rh)) + fr;
+    T xm[1 + D], sm[1 + D];
+    xm[0] = rh;
+#pragma unroll
+    for (int a = 0; a < D; ++a) xm[1 + a] = sg * sj[a];
+    pair_sums(xm, sm);
+    const T rho = sm[0] + fr;
     // original model: u = c j / rho (+ h G), with one division per point
     const T cir = ORIG ? P.c / rho : T(0);
     T G[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)}, us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const T jh = sg * sj[a];
-        const T j = jh + partner(jh);
+        const T j = sm[1 + a];
         if constexpr (NOG) {
             u[a] = ORIG ? cir * j : P.crho * j;
         } else {
@@ -225,12 +280,16 @@ __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT
             if (LAT::e(k, a) == -1) sj[a] -= fb[k];
         }
     }
-    rho = (rh + partner(rh)) + fr;
+    T xm[1 + D], sm[1 + D];
+    xm[0] = rh;
+#pragma unroll
+    for (int a = 0; a < D; ++a) xm[1 + a] = sg * sj[a];
+    pair_sums(xm, sm);
+    rho = sm[0] + fr;
     const T cir = ORIG ? P.c / rho : T(0);  // original model, as in phi_half
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const T jh = sg * sj[a];
-        const T j = jh + partner(jh);
+        const T j = sm[1 + a];
         if constexpr (NOG) u[a] = ORIG ? cir * j : P.crho * j;
         else u[a] = ORIG ? cir * j + (T(0.5) * P.h) * G[a] : vel_from<T, false>(P, rho, j, G[a], T(0.5) * P.h);
     }
@@ -870,13 +929,15 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                     }
                 }
                 const T pr = ph.rest(ph.cur);
-                const T rho = (rh + partner(rh)) + pr;
+                T xm[1 + D], sm[1 + D];
+                xm[0] = rh;
+#pragma unroll
+                for (int a = 0; a < D; ++a) xm[1 + a] = sg * sj[a];
+                pair_sums(xm, sm);
+                const T rho = sm[0] + pr;
                 T us[3] = {T(0), T(0), T(0)};
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const T jh = sg * sj[a];
-                    us[a] = sg * (P.crho * (jh + partner(jh)));
-                }
+                for (int a = 0; a < D; ++a) us[a] = sg * (P.crho * sm[1 + a]);
                 const EqPt<T> E = eq_point<LAT, T, false>(P, rho, us, nullptr);
 #pragma unroll
                 for (int k = 0; k < K; ++k) acc[k] = pv[k] + Bu * (feq_pt<LAT, T, false>(P, E, k) - pv[k]);
