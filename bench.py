@@ -635,7 +635,7 @@ def main():
         b27 = 2.0 * 27 * esize * cells
         also["d3q27"] = {"ms_per_step": round(ms27, 5), "mlups": round(cells / ms27 / 1e3, 2),
                          "hbm_frac": round(b27 / (ms27 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        # configs[2] on the stretched mesh (tanh k = 1.5, Re 1000), both precisions
+        # the 128^3 cavity on the stretched mesh (tanh k = 1.5, Re 1000), both precisions
         for dt_name in ("f64", "f32"):
             ct = cavity_cfg(args.n, dt_name, "tanh", 1000.0)
             f = torch.empty((Q,) + shp, dtype=M.torch_dtype(ct), device="cuda")
