@@ -60,11 +60,31 @@ __device__ __forceinline__ void pair_sum2_u32(unsigned a, unsigned b, unsigned& 
     r0 = r[0];
     r1 = r[1];
 }
-__device__ __forceinline__ void pair_sum2(float a, float b, float& sa, float& sb)
+// M: how the pair is combined: 0 both sums plain; 1 a plain, b signed (the
+// lane's sign sg, +1 in the lower and -1 in the upper half-wave); 2 both
+// signed.  A signed sum is that of sg * x: the lower lane's value minus the
+// upper one's, bitwise what sg * x + partner(sg * x) gives, since
+// multiplying by -1 is exact.
+template <int M>
+__device__ __forceinline__ float pair_combine(float x0, float x1, float sg)
+{
+    if constexpr (M == 0) return x0 + x1;
+    else if constexpr (M == 1) return __builtin_fmaf(sg, x1, x0);
+    else return x0 - x1;
+}
+template <int M>
+__device__ __forceinline__ double pair_combine(double x0, double x1, double sg)
+{
+    if constexpr (M == 0) return x0 + x1;
+    else if constexpr (M == 1) return __builtin_fma(sg, x1, x0);
+    else return x0 - x1;
+}
+template <int M = 0>
+__device__ __forceinline__ void pair_sum2(float a, float b, float& sa, float& sb, float sg = 1.0f)
 {
     unsigned x0, x1;
     pair_sum2_u32(__float_as_uint(a), __float_as_uint(b), x0, x1);
-    const float sum = __uint_as_float(x0) + __uint_as_float(x1);
+    const float sum = pair_combine<M>(__uint_as_float(x0), __uint_as_float(x1), sg);
     unsigned c = __float_as_uint(sum);
     asm volatile("" : "+v"(c));
     unsigned y0, y1;
@@ -72,15 +92,16 @@ __device__ __forceinline__ void pair_sum2(float a, float b, float& sa, float& sb
     sa = __uint_as_float(y0);
     sb = __uint_as_float(y1);
 }
-__device__ __forceinline__ void pair_sum2(double a, double b, double& sa, double& sb)
+template <int M = 0>
+__device__ __forceinline__ void pair_sum2(double a, double b, double& sa, double& sb, double sg = 1.0)
 {
     const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
     const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
     unsigned l0, l1, h0, h1;
     pair_sum2_u32((unsigned)ua, (unsigned)ub, l0, l1);
     pair_sum2_u32((unsigned)(ua >> 32), (unsigned)(ub >> 32), h0, h1);
-    const double sum = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0)) +
-                       __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+    const double sum = pair_combine<M>(__longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0)),
+                                       __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1)), sg);
     const unsigned long long us = (unsigned long long)__double_as_longlong(sum);
     unsigned clo = (unsigned)us, chi = (unsigned)(us >> 32);
     asm volatile("" : "+v"(clo), "+v"(chi));
@@ -89,13 +110,18 @@ __device__ __forceinline__ void pair_sum2(double a, double b, double& sa, double
     sa = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0));
     sb = __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
 }
-// s[i] = x[i] + x[i] of the partner lane (the same column's other half)
-template <int N, typename T>
-__device__ __forceinline__ void pair_sums(const T (&x)[N], T (&s)[N])
+// the moments of a column from the two lanes' partial sums: rho = rh + rh
+// of the partner lane, j[a] = the pair sum of sg * sj[a]
+template <int D, typename T>
+__device__ __forceinline__ void moment_sums(T rh, const T (&sj)[3], T sg, T& rho, T (&j)[3])
 {
-#pragma unroll
-    for (int i = 0; i + 1 < N; i += 2) pair_sum2(x[i], x[i + 1], s[i], s[i + 1]);
-    if constexpr (N % 2 == 1) s[N - 1] = x[N - 1] + partner(x[N - 1]);
+    pair_sum2<1>(rh, sj[0], rho, j[0], sg);
+    if constexpr (D == 3) {
+        pair_sum2<2>(sj[1], sj[2], j[1], j[2], sg);
+    } else {
+        const T x = sg * sj[1];
+        j[1] = x + partner(x);
+    }
 }
 
 // value of lane l + N (N > 0) or l - N (N < 0) of the lane's 16-lane row
@@ -180,25 +206,25 @@ __device__ __forceinline__ void phi_half(const Inst<T>& P, const T (&fv)[LAT::RE
             if (LAT::e(k, a) == -1) sj[a] -= fv[k];
         }
     }
-    T xm[1 + D], sm[1 + D];
-    xm[0] = rh;
-#pragma unroll
-    for (int a = 0; a < D; ++a) xm[1 + a] = sg * sj[a];
-    pair_sums(xm, sm);
-    const T rho = sm[0] + fr;
+    T rs, js[3];
+    moment_sums<D>(rh, sj, sg, rs, js);
+    const T rho = rs + fr;
     // original model: u = c j / rho (+ h G), with one division per point
     const T cir = ORIG ? P.c / rho : T(0);
     T G[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)}, us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
+    // without acceleration the lane-frame velocity directly: (sg c / rho0) j,
+    // bitwise sg (c j / rho0)
+    const T cu = sg * (ORIG ? cir : P.crho);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const T j = sm[1 + a];
+        const T j = js[a];
         if constexpr (NOG) {
-            u[a] = ORIG ? cir * j : P.crho * j;
+            us[a] = cu * j;
         } else {
             G[a] = gt * (P.G0[a] + (has_field ? fg[a] : T(0)));
             u[a] = ORIG ? cir * j + P.h * G[a] : vel_from<T, false>(P, rho, j, G[a], P.h);
+            us[a] = sg * u[a];
         }
-        us[a] = sg * u[a];
         Gs[a] = sg * G[a];
     }
     // NOG: no acceleration at all, the source term of Eq. (S) vanishes
@@ -265,7 +291,9 @@ __device__ __forceinline__ void recon_half(const Inst<T>& P, const ACC& ph, int 
 }
 
 // interface moments (Eq. macro_values at the interface) from the two lanes' values
-template <class LAT, typename T, bool NOG = false, bool ORIG = false>
+// LANE: u receives the velocity in the lane's frame, sg u (without
+// acceleration: (sg c / rho0) j, bitwise sg (c j / rho0))
+template <class LAT, typename T, bool NOG = false, bool ORIG = false, bool LANE = false>
 __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT::REST], T fr, const T* G, T sg,
                                              T& rho, T* u)
 {
@@ -280,18 +308,20 @@ __device__ __forceinline__ void moments_half(const Inst<T>& P, const T (&fb)[LAT
             if (LAT::e(k, a) == -1) sj[a] -= fb[k];
         }
     }
-    T xm[1 + D], sm[1 + D];
-    xm[0] = rh;
-#pragma unroll
-    for (int a = 0; a < D; ++a) xm[1 + a] = sg * sj[a];
-    pair_sums(xm, sm);
-    rho = sm[0] + fr;
+    T rs, js[3];
+    moment_sums<D>(rh, sj, sg, rs, js);
+    rho = rs + fr;
     const T cir = ORIG ? P.c / rho : T(0);  // original model, as in phi_half
+    const T cu = LANE ? sg * (ORIG ? cir : P.crho) : (ORIG ? cir : P.crho);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const T j = sm[1 + a];
-        if constexpr (NOG) u[a] = ORIG ? cir * j : P.crho * j;
-        else u[a] = ORIG ? cir * j + (T(0.5) * P.h) * G[a] : vel_from<T, false>(P, rho, j, G[a], T(0.5) * P.h);
+        const T j = js[a];
+        if constexpr (NOG) {
+            u[a] = cu * j;
+        } else {
+            const T ua = ORIG ? cir * j + (T(0.5) * P.h) * G[a] : vel_from<T, false>(P, rho, j, G[a], T(0.5) * P.h);
+            u[a] = LANE ? sg * ua : ua;
+        }
     }
 #pragma unroll
     for (int a = D; a < 3; ++a) u[a] = T(0);
@@ -500,14 +530,11 @@ __device__ __forceinline__ void face_half(const Inst<T>& P, const ACC& ph, const
     else face_force<LAT, T>(P, force, A, f, w, ci, gth, G);
     if (wall_lo) wall_half<LAT, T, A, ORIG>(P, 2 * A, -1, fb, info, sg, sgi, gth);
     if (wall_hi) wall_half<LAT, T, A, ORIG>(P, 2 * A + 1, 1, fb, info, sg, sgi, gth);
-    T rho, u[3];
-    moments_half<LAT, T, NOG, ORIG>(P, fb, fr, G, sg, rho, u);
-    T us[3] = {T(0), T(0), T(0)}, Gs[3] = {T(0), T(0), T(0)};
+    T rho, us[3];
+    moments_half<LAT, T, NOG, ORIG, true>(P, fb, fr, G, sg, rho, us);
+    T Gs[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int a = 0; a < LAT::D; ++a) {
-        us[a] = sg * u[a];
-        Gs[a] = sg * G[a];
-    }
+    for (int a = 0; a < LAT::D; ++a) Gs[a] = sg * G[a];
     const EqPt<T> E = eq_point<LAT, T, ORIG>(P, rho, us, NOG ? nullptr : Gs);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -929,15 +956,12 @@ __device__ __forceinline__ void split_body(const Inst<T>& P, const T* __restrict
                     }
                 }
                 const T pr = ph.rest(ph.cur);
-                T xm[1 + D], sm[1 + D];
-                xm[0] = rh;
-#pragma unroll
-                for (int a = 0; a < D; ++a) xm[1 + a] = sg * sj[a];
-                pair_sums(xm, sm);
-                const T rho = sm[0] + pr;
+                T rs, js[3];
+                moment_sums<D>(rh, sj, sg, rs, js);
+                const T rho = rs + pr;
                 T us[3] = {T(0), T(0), T(0)};
 #pragma unroll
-                for (int a = 0; a < D; ++a) us[a] = sg * (P.crho * sm[1 + a]);
+                for (int a = 0; a < D; ++a) us[a] = sg * (P.crho * js[a]);
                 const EqPt<T> E = eq_point<LAT, T, false>(P, rho, us, nullptr);
 #pragma unroll
                 for (int k = 0; k < K; ++k) acc[k] = pv[k] + Bu * (feq_pt<LAT, T, false>(P, E, k) - pv[k]);
